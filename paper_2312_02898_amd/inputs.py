@@ -1,0 +1,115 @@
+"""Seeded synthetic inputs: RAMBO phase-space points.
+
+This module only generates momenta.  It holds none of the matrix-element
+arithmetic and imports nothing else from the package, so the tests can feed
+the same events to the GPU path and to the CPU oracle.
+
+RAMBO (Kleiss, Stirling, Ellis, Comput. Phys. Commun. 40 (1986) 359) is the
+flat multi-particle generator the paper's standalone test-bed uses to make
+batches of test events for throughput measurements (Sec. 2).  Readings where
+the paper is silent:
+  * random numbers: ``numpy.random.Generator(PCG64(seed))`` uniform doubles,
+    drawn event-major, final-particle-major, 4 per particle; a uniform u in
+    [0,1) enters the logarithm as 1-u (so it lies in (0,1]);
+  * incoming legs are massless and lie on the beam axis in the centre-of-mass
+    frame: p1 = (sqrt(s)/2)(1,0,0,1), p2 = (sqrt(s)/2)(1,0,0,-1);
+  * massive final states: the massless momenta are rescaled by xi solving
+    sum_i sqrt(m_i^2 + xi^2 p0_i^2) = sqrt(s) with Newton's method from
+    xi0 = sqrt(1 - (sum m / sqrt s)^2), stopping at |residual| <= 1e-14 sqrt(s)
+    or after 50 steps.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# Leg masses of the benchmark processes (GeV): top = 173, everything else 0.
+PROCESS_LEGS = {
+    "e+ e- > mu+ mu-": (0.0, 0.0, 0.0, 0.0),
+    "g g > t t~": (0.0, 0.0, 173.0, 173.0),
+    "g g > t t~ g": (0.0, 0.0, 173.0, 173.0, 0.0),
+    "g g > t t~ g g": (0.0, 0.0, 173.0, 173.0, 0.0, 0.0),
+    "g g > t t~ g g g": (0.0, 0.0, 173.0, 173.0, 0.0, 0.0, 0.0),
+}
+
+
+def rambo(nevt: int, sqrt_s: float, final_masses, seed: int, rng=None) -> np.ndarray:
+    """Return float64 momenta [nevt][2 + nfinal][4] as (E, px, py, pz)."""
+    masses = np.asarray(final_masses, dtype=np.float64)
+    n = masses.size
+    if rng is None:
+        rng = np.random.Generator(np.random.PCG64(seed))
+    r = rng.random((nevt, n, 4))
+    c = 2.0 * r[..., 0] - 1.0
+    phi = 2.0 * np.pi * r[..., 1]
+    q0 = -np.log((1.0 - r[..., 2]) * (1.0 - r[..., 3]))
+    st = np.sqrt(np.maximum(0.0, 1.0 - c * c))
+    q = np.empty((nevt, n, 4))
+    q[..., 0] = q0
+    q[..., 1] = q0 * st * np.cos(phi)
+    q[..., 2] = q0 * st * np.sin(phi)
+    q[..., 3] = q0 * c
+    Q = q.sum(axis=1)
+    M = np.sqrt(Q[:, 0] ** 2 - Q[:, 1] ** 2 - Q[:, 2] ** 2 - Q[:, 3] ** 2)
+    b = -Q[:, 1:] / M[:, None]
+    gamma = Q[:, 0] / M
+    a = 1.0 / (1.0 + gamma)
+    x = sqrt_s / M
+    bq = np.einsum("ek,enk->en", b, q[..., 1:])
+    p = np.empty_like(q)
+    p[..., 0] = x[:, None] * (gamma[:, None] * q[..., 0] + bq)
+    p[..., 1:] = x[:, None, None] * (q[..., 1:] + b[:, None, :] * q[..., 0:1]
+                                     + a[:, None, None] * bq[..., None] * b[:, None, :])
+    if np.any(masses > 0):
+        p = _rescale_massive(p, masses, sqrt_s)
+    out = np.empty((nevt, n + 2, 4))
+    e = 0.5 * sqrt_s
+    out[:, 0] = (e, 0.0, 0.0, e)
+    out[:, 1] = (e, 0.0, 0.0, -e)
+    out[:, 2:] = p
+    return out
+
+
+def _rescale_massive(p: np.ndarray, masses: np.ndarray, sqrt_s: float) -> np.ndarray:
+    if masses.sum() >= sqrt_s:
+        raise ValueError("sqrt(s) below the production threshold")
+    m2 = masses[None, :] ** 2
+    p02 = p[..., 0] ** 2
+    xi = np.full(p.shape[0], np.sqrt(1.0 - (masses.sum() / sqrt_s) ** 2))
+    for _ in range(50):
+        e = np.sqrt(m2 + (xi[:, None] ** 2) * p02)
+        f = e.sum(axis=1) - sqrt_s
+        todo = np.abs(f) > 1e-14 * sqrt_s      # per event, so a batch's prefix is reproducible
+        if not np.any(todo):
+            break
+        df = (xi[:, None] * p02 / e).sum(axis=1)
+        xi = np.where(todo, xi - f / df, xi)
+    k = np.empty_like(p)
+    k[..., 1:] = xi[:, None, None] * p[..., 1:]
+    k[..., 0] = np.sqrt(m2 + (xi[:, None] ** 2) * p02)
+    return k
+
+
+def process_events(process: str, nevt: int, sqrt_s: float, seed: int) -> np.ndarray:
+    """RAMBO events for one of the benchmark processes (leg order of the
+    process string, legs 0 and 1 incoming)."""
+    masses = PROCESS_LEGS[process]
+    if any(m != 0 for m in masses[:2]):
+        raise ValueError("massive incoming legs are not supported")
+    return rambo(nevt, sqrt_s, masses[2:], seed)
+
+
+# The benchmark configurations: process, sqrt(s) in GeV, number of events, seed.
+CONFIGS = {
+    "eemumu": ("e+ e- > mu+ mu-", 500.0, 16384, 1),
+    "ggtt": ("g g > t t~", 1500.0, 1 << 19, 2),
+    "ggttg": ("g g > t t~ g", 1500.0, 1 << 20, 3),
+    "ggttgg": ("g g > t t~ g g", 1500.0, 1 << 20, 4),
+    "ggttggg": ("g g > t t~ g g g", 1500.0, 1 << 20, 5),
+}
+
+
+def config_events(name: str, nevt: int | None = None) -> np.ndarray:
+    """Events of a named benchmark configuration.  A prefix of the full batch
+    when nevt is smaller (the draws are event-major, so prefixes agree)."""
+    process, sqrt_s, n_full, seed = CONFIGS[name]
+    return process_events(process, n_full if nevt is None else nevt, sqrt_s, seed)

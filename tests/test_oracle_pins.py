@@ -1,0 +1,420 @@
+"""Pins of the CPU oracle against results that do not come from the oracle.
+
+Each test checks the oracle against something the mathematics fixes: closed
+forms, trace-technique spin sums with explicit gamma matrices, gauge and
+Lorentz invariance, Bose symmetry, helicity-selection rules, the literal
+colour-dressed Feynman rules, colour identities and a total cross section.
+A plausible mistake anywhere in the oracle (a dropped diagram, a wrong
+sign, index or coupling, a transposed operand, a missing symmetry factor)
+fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2312_02898_amd.inputs import config_events, rambo
+
+G = np.diag([1.0, -1.0, -1.0, -1.0])
+ALPHA = 1.0 / 132.507
+ALPHA_S = 0.118
+MT = 173.0
+MZ, WZ = 91.188, 2.441
+SW2 = 0.2222
+
+
+def mdot(a, b):
+    return a[..., 0] * b[..., 0] - (a[..., 1:] * b[..., 1:]).sum(-1)
+
+
+# ----------------------------------------------------------- closed forms
+def ee_closed_form(p):
+    """e+(p1) e-(p2) -> mu+(p3) mu-(p4) via photon and Z, massless leptons:
+    (e^4/4)[(|A_LL|^2+|A_RR|^2)(1+cos)^2 + (|A_LR|^2+|A_RL|^2)(1-cos)^2],
+    A_ij = Q_e Q_mu + c_i c_j s/(s - MZ^2 + i MZ GZ)."""
+    s = mdot(p[:, 0] + p[:, 1], p[:, 0] + p[:, 1])
+    e2 = 4 * np.pi * ALPHA
+    sw, cw = np.sqrt(SW2), np.sqrt(1 - SW2)
+    cl, cr = (-0.5 + SW2) / (sw * cw), SW2 / (sw * cw)
+    chi = s / (s - MZ ** 2 + 1j * MZ * WZ)
+    onepc = -2 * mdot(p[:, 1] - p[:, 2], p[:, 1] - p[:, 2]) / s
+    onemc = -2 * mdot(p[:, 1] - p[:, 3], p[:, 1] - p[:, 3]) / s
+
+    def A(ci, cj):
+        return 1 + ci * cj * chi
+    return e2 ** 2 / 4 * ((abs(A(cl, cl)) ** 2 + abs(A(cr, cr)) ** 2) * onepc ** 2
+                          + (abs(A(cl, cr)) ** 2 + abs(A(cr, cl)) ** 2) * onemc ** 2)
+
+
+def ggtt_closed_form(p, m=MT):
+    """Combridge / Glueck-Owens-Reya: g^4 (1/(6 t1 t2) - 3/8)(t1^2 + t2^2 + rho
+    - rho^2/(4 t1 t2)), t1 = 2 p1.p3/s, t2 = 2 p2.p3/s, rho = 4 m^2/s."""
+    s = mdot(p[:, 0] + p[:, 1], p[:, 0] + p[:, 1])
+    g2 = 4 * np.pi * ALPHA_S
+    t1 = 2 * mdot(p[:, 0], p[:, 2]) / s
+    t2 = 2 * mdot(p[:, 1], p[:, 2]) / s
+    rho = 4 * m * m / s
+    return g2 ** 2 * (1 / (6 * t1 * t2) - 3 / 8) * (t1 ** 2 + t2 ** 2 + rho - rho ** 2 / (4 * t1 * t2))
+
+
+def test_eemumu_closed_form(oracle_lib):
+    p = config_events("eemumu", 4096)
+    o = oracle_lib.me("e+ e- > mu+ mu-", p)
+    rel = np.abs(o / ee_closed_form(p) - 1)
+    # the closed form's (p2-p3)^2 loses digits at near-collinear points
+    assert np.median(rel) < 1e-15 and rel.max() < 1e-11, rel.max()
+
+
+def test_ggtt_closed_form(oracle_lib):
+    p = config_events("ggtt", 4096)
+    o = oracle_lib.me("g g > t t~", p)
+    rel = np.abs(o / ggtt_closed_form(p) - 1)
+    assert np.median(rel) < 1e-14 and rel.max() < 1e-11, rel.max()
+
+
+def test_ggtt_massless_limit(oracle_lib):
+    """m -> 0: g^4 [(t^2+u^2)/(6tu) - 3(t^2+u^2)/(8 s^2)]."""
+    p = rambo(512, 1500.0, [0.0, 0.0], seed=11)
+    o = oracle_lib.me("g g > t t~", p, oracle_lib.default_params(mt=0.0, wt=0.0))
+    s = mdot(p[:, 0] + p[:, 1], p[:, 0] + p[:, 1])
+    t = mdot(p[:, 0] - p[:, 2], p[:, 0] - p[:, 2])
+    u = mdot(p[:, 0] - p[:, 3], p[:, 0] - p[:, 3])
+    g4 = (4 * np.pi * ALPHA_S) ** 2
+    ref = g4 * ((t * t + u * u) / (6 * t * u) - 3 * (t * t + u * u) / (8 * s * s))
+    assert np.abs(o / ref - 1).max() < 1e-11
+
+
+def test_ggtt_threshold(oracle_lib):
+    """At threshold every angle gives 7 g^4 / 48."""
+    p = rambo(64, 2 * MT * (1 + 1e-9), [MT, MT], seed=12)
+    o = oracle_lib.me("g g > t t~", p)
+    ref = 7 * (4 * np.pi * ALPHA_S) ** 2 / 48
+    assert np.abs(o / ref - 1).max() < 1e-6
+
+
+# --------------------------------------------------------- trace technique
+def _gammas():
+    """Chiral representation (the oracle itself uses the Dirac one)."""
+    s = [np.array([[0, 1], [1, 0]], complex), np.array([[0, -1j], [1j, 0]]),
+         np.array([[1, 0], [0, -1]], complex)]
+    z, one = np.zeros((2, 2), complex), np.eye(2, dtype=complex)
+    g = [np.block([[z, one], [one, z]])] + [np.block([[z, si], [-si, z]]) for si in s]
+    g5 = np.block([[-one, z], [z, one]])
+    return np.array(g), g5
+
+
+GAM, G5 = _gammas()
+
+
+def slash(p):
+    return np.einsum("m,mij->ij", G @ p, GAM)
+
+
+def gbar(M):
+    return GAM[0] @ M.conj().T @ GAM[0]
+
+
+def ggtt_trace(p1, p2, p3, p4, m=MT, width=0.0):
+    """sum over spins, physical gluon polarisations and colours of |M|^2 / 256,
+    from Tr[(p3/+m) Gamma (p4/-m) Gamma-bar] with the three diagrams written
+    as 4x4 matrices and the two colour structures t^a t^b, t^b t^a."""
+    g2 = 4 * np.pi * ALPHA_S
+    I4 = np.eye(4)
+    t = mdot(p3 - p1, p3 - p1)
+    u = mdot(p3 - p2, p3 - p2)
+    s = mdot(p1 + p2, p1 + p2)
+    Tm = np.zeros((4, 4, 4, 4), complex)
+    Um = np.zeros_like(Tm)
+    Sm = np.zeros_like(Tm)
+    prop_t = slash(p3 - p1) + m * I4
+    prop_u = slash(p3 - p2) + m * I4
+    k, pp, q = p1, p2, -p1 - p2
+    for mu in range(4):
+        for nu in range(4):
+            Tm[mu, nu] = -1j * g2 * GAM[mu] @ prop_t @ GAM[nu] / (t - m * m + 1j * m * width)
+            Um[mu, nu] = -1j * g2 * GAM[nu] @ prop_u @ GAM[mu] / (u - m * m + 1j * m * width)
+            # V^{mu nu rho} = g^{mu nu}(k-p)^rho + g^{nu rho}(p-q)^mu + g^{rho mu}(q-k)^nu
+            Vr = np.array([G[mu, nu] * (k - pp)[r] + G[nu, r] * (pp - q)[mu] + G[r, mu] * (q - k)[nu]
+                           for r in range(4)])
+            Sm[mu, nu] = g2 / s * np.einsum("r,rij->ij", G @ Vr, GAM)
+    Gam = [Tm - 1j * Sm, Um + 1j * Sm]
+    CF, N = 4.0 / 3.0, 3.0
+    Cmat = np.array([[N * CF * CF, -CF / 2], [-CF / 2, N * CF * CF]])
+
+    def polsum(kk, n):
+        kl, nl = G @ kk, G @ n
+        return -G + (np.outer(kl, nl) + np.outer(nl, kl)) / mdot(kk, n)
+    P1, P2 = polsum(p1, p2), polsum(p2, p1)
+    A = slash(p3) + m * I4
+    B = slash(p4) - m * I4
+    tot = 0.0
+    for a in range(2):
+        for b in range(2):
+            Gb = np.array([[gbar(Gam[b][m1, n1]) for n1 in range(4)] for m1 in range(4)])
+            tr = np.einsum("ij,mnjk,kl,MNli->mnMN", A, Gam[a], B, Gb)
+            tot += Cmat[a, b] * np.einsum("mM,nN,mnMN->", P1, P2, tr)
+    return tot.real / 256.0
+
+
+def eemumu_trace(p1, p2, p3, p4):
+    e = math.sqrt(4 * math.pi * ALPHA)
+    sw, cw = math.sqrt(SW2), math.sqrt(1 - SW2)
+    cl, cr = (-0.5 + SW2) / (sw * cw), SW2 / (sw * cw)
+    PL, PR = (np.eye(4) - G5) / 2, (np.eye(4) + G5) / 2
+    q = p1 + p2
+    s = mdot(q, q)
+    verts = {
+        "a": [-1j * e * (-1) * GAM[mu] for mu in range(4)],
+        "z": [-1j * e * GAM[mu] @ (cl * PL + cr * PR) for mu in range(4)],
+    }
+    ql = G @ q
+    props = {"a": -1j * G / s,
+             "z": -1j * (G - np.outer(ql, ql) / MZ ** 2) / (s - MZ ** 2 + 1j * MZ * WZ)}
+    tot = 0.0
+    for V in "az":
+        for W in "az":
+            L1 = np.array([[np.trace(verts[V][mu] @ slash(p2) @ gbar(verts[W][nu]) @ slash(p1))
+                            for nu in range(4)] for mu in range(4)])
+            L2 = np.array([[np.trace(verts[V][mu] @ slash(p3) @ gbar(verts[W][nu]) @ slash(p4))
+                            for nu in range(4)] for mu in range(4)])
+            tot += np.einsum("mn,MN,mM,nN->", props[V], props[W].conj(), L1, L2)
+    return tot.real / 4.0
+
+
+def test_ggtt_trace_bruteforce(oracle_lib):
+    """Spin sums without spinors, for both settings of the t-channel width."""
+    p = config_events("ggtt", 6)
+    for flag in (0, 1):
+        o = oracle_lib.me("g g > t t~", p, oracle_lib.default_params(tchan_zero_width=flag))
+        ref = np.array([ggtt_trace(*ev, width=0.0 if flag else 1.49) for ev in p])
+        assert np.abs(o / ref - 1).max() < 1e-12
+
+
+def test_eemumu_trace_bruteforce(oracle_lib):
+    p = config_events("eemumu", 6)
+    o = oracle_lib.me("e+ e- > mu+ mu-", p)
+    ref = np.array([eemumu_trace(*ev) for ev in p])
+    assert np.abs(o / ref - 1).max() < 1e-12
+
+
+# ------------------------------------------------------------- invariances
+QCD = [("ggtt", "g g > t t~"), ("ggttg", "g g > t t~ g"), ("ggttgg", "g g > t t~ g g"),
+       ("ggttggg", "g g > t t~ g g g")]
+
+
+@pytest.mark.parametrize("cfg,proc", QCD)
+def test_gauge_invariance(oracle_lib, cfg, proc):
+    """Replacing one gluon's polarisation by k/k^0 makes every colour-ordered
+    partial amplitude vanish (zero top width: a fixed width breaks gauge
+    invariance at order Gamma/m)."""
+    prm = oracle_lib.default_params(wt=0.0)
+    npar = oracle_lib.npar(proc)
+    p = config_events(cfg, 3)
+    gluon_legs = [0, 1] + list(range(4, npar))
+    rng = np.random.default_rng(7)
+    for ev in p:
+        hels = rng.choice(1 << npar, size=4, replace=False)
+        scale = max(np.abs(oracle_lib.partial_amps(proc, ev, int(h), params=prm)).max()
+                    for h in range(1 << npar))
+        for h in hels:
+            for leg in gluon_legs:
+                a = oracle_lib.partial_amps(proc, ev, int(h), gauge_leg=leg, params=prm)
+                assert np.abs(a).max() < 1e-12 * scale
+
+
+def _boost(p, beta_vec):
+    b2 = beta_vec @ beta_vec
+    gam = 1 / np.sqrt(1 - b2)
+    bp = p[..., 1:] @ beta_vec
+    out = np.empty_like(p)
+    out[..., 0] = gam * (p[..., 0] + bp)
+    out[..., 1:] = p[..., 1:] + ((gam - 1) * bp / b2 + gam * p[..., 0])[..., None] * beta_vec
+    return out
+
+
+def _rotation(rng):
+    q, r = np.linalg.qr(rng.normal(size=(3, 3)))
+    q = q * np.sign(np.diag(r))
+    if np.linalg.det(q) < 0:
+        q[:, 0] *= -1
+    return q
+
+
+ALL = [("eemumu", "e+ e- > mu+ mu-")] + QCD
+
+
+@pytest.mark.parametrize("cfg,proc", ALL)
+def test_lorentz_and_parity_invariance(oracle_lib, cfg, proc):
+    """Random rotation + boost (beta = 0.9) and spatial parity leave the
+    helicity-summed |M|^2 unchanged.  Zero top width: with a fixed width the
+    amplitude is not gauge invariant, so the sum over the two physical
+    polarisations depends on the frame at order Gamma/m."""
+    n = 16 if cfg != "ggttggg" else 4
+    p = config_events(cfg, n)
+    prm = oracle_lib.default_params(wt=0.0)
+    ref = oracle_lib.me(proc, p, prm)
+    rng = np.random.default_rng(3)
+    beta = rng.normal(size=3)
+    beta *= 0.9 / np.linalg.norm(beta)
+    R = _rotation(rng)
+    q = p.copy()
+    q[..., 1:] = q[..., 1:] @ R.T
+    q = _boost(q, beta)
+    assert np.abs(oracle_lib.me(proc, q, prm) / ref - 1).max() < 1e-11
+    par = p.copy()
+    par[..., 1:] *= -1
+    assert np.abs(oracle_lib.me(proc, par, prm) / ref - 1).max() < 1e-12
+
+
+@pytest.mark.parametrize("cfg,proc", QCD)
+def test_bose_symmetry(oracle_lib, cfg, proc):
+    n = 16 if cfg != "ggttggg" else 4
+    p = config_events(cfg, n)
+    ref = oracle_lib.me(proc, p)
+    sw = p[:, [1, 0] + list(range(2, p.shape[1]))]
+    assert np.abs(oracle_lib.me(proc, sw) / ref - 1).max() < 1e-12
+    npar = p.shape[1]
+    if npar >= 6:
+        perm = list(range(npar))
+        perm[4], perm[npar - 1] = perm[npar - 1], perm[4]
+        assert np.abs(oracle_lib.me(proc, p[:, perm]) / ref - 1).max() < 1e-12
+
+
+# ---------------------------------------------------- helicity selection
+@pytest.mark.parametrize("cfg,proc,nlive", [("eemumu", "e+ e- > mu+ mu-", 4),
+                                             ("ggtt", "g g > t t~", 4),
+                                             ("ggttg", "g g > t t~ g", 12),
+                                             ("ggttgg", "g g > t t~ g g", 28),
+                                             ("ggttggg", "g g > t t~ g g g", 60)])
+def test_massless_helicity_count(oracle_lib, cfg, proc, nlive):
+    """Massless quarks: helicity is conserved along each fermion line and a
+    tree amplitude with all gluon helicities equal (or all but one) vanishes,
+    leaving 2(2^n - 2) live configurations for ttbar + n gluons; ee->mumu has 4."""
+    npar = oracle_lib.npar(proc)
+    masses = [0.0] * (npar - 2)
+    p = rambo(3, 1500.0, masses, seed=21)
+    prm = oracle_lib.default_params(mt=0.0, wt=0.0)
+    mh = oracle_lib.me_hel(proc, p, prm)
+    live = (mh / mh.sum(axis=1, keepdims=True)).max(axis=0) > 1e-20
+    assert live.sum() == nlive
+
+
+def test_ggtt_massive_cm_helicities(oracle_lib):
+    """With m_t = 173 in the CM frame exactly the 4 configurations with equal
+    gluon helicities and opposite t/tbar helicities vanish; the zeros are a
+    property of the frame (they come back to life after a transverse boost)."""
+    p = config_events("ggtt", 8)
+    mh = oracle_lib.me_hel("g g > t t~", p)
+    r = mh / mh.sum(axis=1, keepdims=True)
+    dead = sorted(np.nonzero(r.max(axis=0) < 1e-24)[0].tolist())
+    # bit i = leg i helicity: legs (g, g, t, tbar)
+    assert dead == [4, 7, 8, 11]
+    q = _boost(p, np.array([0.5, 0.0, 0.0]))
+    mq = oracle_lib.me_hel("g g > t t~", q)
+    assert (mq / mq.sum(axis=1, keepdims=True)).max(axis=0).min() > 1e-6
+
+
+# ------------------------------------------------------------- rounding
+@pytest.mark.parametrize("cfg,proc", ALL)
+def test_long_double_agrees(oracle_lib, cfg, proc):
+    n = 32 if cfg != "ggttggg" else 4
+    p = config_events(cfg, n)
+    d = oracle_lib.me(proc, p)
+    ld = oracle_lib.me(proc, p, long_double=True)
+    assert np.median(np.abs(d / ld - 1)) < 1e-14
+    assert np.abs(d / ld - 1).max() < 1e-12
+
+
+# ------------------------------------------------------------------ colour
+@pytest.mark.parametrize("proc,ng", [("g g > t t~", 2), ("g g > t t~ g", 3),
+                                     ("g g > t t~ g g", 4), ("g g > t t~ g g g", 5)])
+def test_colour_ordered_matches_colour_dressed(oracle_lib, proc, ng):
+    """Full amplitude from literal f^{abc}, t^a rules with explicit colours
+    equals sum_sigma c_sigma A(sigma) from the colour-ordered recursion."""
+    cfg = {2: "ggtt", 3: "ggttg", 4: "ggttgg", 5: "ggttggg"}[ng]
+    p = config_events(cfg, 2)
+    rng = np.random.default_rng(ng)
+    npar = oracle_lib.npar(proc)
+    checked = 0
+    tries = 0
+    while checked < (6 if ng < 5 else 2) and tries < 5000:
+        tries += 1
+        # colours 0..2 (lambda_1..3) and 7 (lambda_8) keep most strings non-zero
+        col = list(rng.choice([0, 1, 2, 3, 4, 7], size=ng)) + list(rng.integers(0, 3, size=2))
+        c = oracle_lib.colour_basis(ng, col)
+        if np.abs(c).max() == 0:
+            continue
+        ev = p[checked % 2]
+        h = int(rng.integers(0, 1 << npar))
+        A = oracle_lib.partial_amps(proc, ev, h)
+        m1 = (c * A).sum()
+        m2 = oracle_lib.dressed_amp(proc, ev, h, col)
+        amax = max(np.abs(oracle_lib.partial_amps(proc, ev, hh)).max() for hh in range(1 << npar))
+        scale = np.abs(c).max() * amax
+        assert abs(m1 - m2) < 1e-12 * scale
+        checked += 1
+    assert checked >= 2
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+def test_colour_matrix_identities(oracle_lib, n):
+    """C_ss = N C_F^n (t^a t^a = C_F 1); C real, symmetric, positive definite;
+    C_{sigma tau} depends only on sigma^-1 tau (renaming summed indices);
+    entries are rationals with a small common denominator."""
+    import itertools
+    C = oracle_lib.colour_matrix(n)
+    N, CF = 3.0, 4.0 / 3.0
+    assert np.allclose(np.diag(C), N * CF ** n, rtol=1e-13)
+    assert np.array_equal(C, C.T)
+    assert np.linalg.eigvalsh(C).min() > 0.5
+    perms = list(itertools.permutations(range(n)))
+    index = {pp: i for i, pp in enumerate(perms)}
+    for s_i, s in enumerate(perms[:3]):
+        inv = [0] * n
+        for k, v in enumerate(s):
+            inv[v] = k
+        for t_i, t in enumerate(perms):
+            rel = tuple(inv[t[k]] for k in range(n))
+            assert abs(C[s_i, t_i] - C[0, index[rel]]) < 1e-11
+    den = {1: 1, 2: 3, 3: 9, 4: 54, 5: 324}[n]
+    assert np.abs(C * den - np.round(C * den)).max() < 1e-9
+    if n == 2:
+        # Tr(t^b t^a t^b t^a) = -C_F/2 (t^b t^a t^b = -t^a / (2N))
+        assert abs(C[0, 1] + CF / 2) < 1e-14
+
+
+# ------------------------------------------------------ total cross section
+def test_ggtt_cross_section(oracle_lib):
+    """RAMBO Monte-Carlo integral of the oracle over 2-body phase space equals
+    sigma = pi alpha_s^2/(3s) [(1 + rho + rho^2/16) ln((1+beta)/(1-beta))
+    - beta (7/4 + 31 rho/16)] (pins RAMBO and the overall normalisation)."""
+    sqs = 1500.0
+    p = rambo(1 << 15, sqs, [MT, MT], seed=31)
+    me = oracle_lib.me("g g > t t~", p)
+    s = sqs * sqs
+    rho = 4 * MT * MT / s
+    beta = math.sqrt(1 - rho)
+    flux_ps = beta / (8 * math.pi) / (2 * s)
+    mc = flux_ps * me.mean()
+    err = flux_ps * me.std() / math.sqrt(me.size)
+    ref = math.pi * ALPHA_S ** 2 / (3 * s) * ((1 + rho + rho * rho / 16) * math.log((1 + beta) / (1 - beta))
+                                              - beta * (7 / 4 + 31 * rho / 16))
+    assert abs(mc - ref) < 4 * err
+    assert err / ref < 0.01
+
+
+# ------------------------------------------------------------------ RAMBO
+@pytest.mark.parametrize("cfg", ["eemumu", "ggtt", "ggttg", "ggttgg", "ggttggg"])
+def test_rambo_kinematics(cfg):
+    p = config_events(cfg, 2000)
+    sqs = mdot(p[:, 0] + p[:, 1], p[:, 0] + p[:, 1]) ** 0.5
+    bal = p[:, 0] + p[:, 1] - p[:, 2:].sum(axis=1)
+    assert np.abs(bal).max() < 1e-12 * sqs.max()
+    m2 = mdot(p, p)
+    masses = np.array([0, 0, 173.0, 173.0, 0, 0, 0][:p.shape[1]]) if cfg != "eemumu" else np.zeros(4)
+    assert np.abs(m2 - masses ** 2).max() < 1e-9 * sqs.max() ** 2
+    assert (p[..., 0] > 0).all()
+    # isotropy of the final state: <cos theta> ~ 0
+    c = p[:, 2:, 3] / np.linalg.norm(p[:, 2:, 1:], axis=-1)
+    assert abs(c.mean()) < 5 / math.sqrt(c.size)
+    assert np.array_equal(config_events(cfg, 10), p[:10])
