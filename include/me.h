@@ -1,0 +1,186 @@
+/*
+ * me.h -- C ABI of the MI355X (gfx950) leading-order matrix-element engine.
+ *
+ * The engine evaluates, for a batch of phase-space points ("events"), the
+ * spin- and colour-summed, initial-state averaged squared matrix element
+ * |M|^2 of a fixed tree-level process: the quantity the paper (Sec. 2 and
+ * Sec. 3) identifies as the most expensive part of event generation and
+ * offloads to GPUs with event-level data parallelism.  Per event the device
+ * computes external wavefunctions, HELAS-style vertex and propagator calls for
+ * every Feynman diagram and helicity, the colour-flow amplitudes jamp, the
+ * colour sum jamp^H C jamp and the helicity sum.
+ *
+ * Supported processes (Summary section of the paper: LO QED/QCD; the
+ * processes validated there are e+e- -> mu+mu- and gg -> ttbar + 0..3 g):
+ *     "e+ e- > mu+ mu-"  "g g > t t~"  "g g > t t~ g"  "g g > t t~ g g"
+ *
+ * Conventions
+ *   momenta   const double mom[nevt][npar][4], (E, px, py, pz) in GeV, in
+ *             DEVICE memory, legs in the order of the process string, legs 0
+ *             and 1 incoming.  Events must be in the partonic centre-of-mass
+ *             frame with the beams along +-z: the helicity filter's list of
+ *             vanishing helicities is frame dependent for massive legs.
+ *   output    double me[nevt] in device memory, in GeV^(4-2n) for 2 -> n.
+ *   helicity  configuration h in [0, 2^npar): leg i has helicity +1 iff bit i
+ *             of h is set.
+ *   widths    fixed-width propagators; in the "zero-width t-channel mode" of
+ *             the paper (Sec. 3, Tables 1-2) the top width is 0 in every
+ *             propagator whose momentum is the sum of exactly one incoming
+ *             leg and some outgoing legs.
+ *
+ * Ownership and threading
+ *   A handle owns its device constants; the caller owns momenta, outputs and
+ *   streams.  me_compute is asynchronous and stream-ordered: results are valid
+ *   once the stream has been synchronised, and the inputs must stay alive until
+ *   then.  After me_helicity_filter a handle is read-only, so me_compute may be
+ *   called concurrently on several streams.  me_destroy must not race with
+ *   work in flight.
+ *
+ * Errors
+ *   Every function returns an me_status; 0 is success.  Null pointers and
+ *   negative sizes give ME_EINVAL, an unknown process ME_EPROCESS, a failed
+ *   allocation ME_ENOMEM, a failed HIP call ME_EHIP.  nevt == 0 is a no-op.
+ *   me_last_error() returns a thread-local message for the last failure.
+ *   Momentum values are not validated on the hot path.
+ */
+#ifndef ME_H
+#define ME_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct me_handle_s* me_handle;
+typedef int32_t me_status;
+
+enum {
+  ME_OK = 0,
+  ME_EINVAL = -1,
+  ME_EPROCESS = -2,
+  ME_ENOMEM = -3,
+  ME_EHIP = -4,
+  ME_ENOTSUP = -5,
+  ME_EBUSY = -6
+};
+
+typedef enum {
+  ME_FP64 = 0,  /* all arithmetic in FP64 */
+  ME_MIXED = 1  /* FP32 wavefunctions and vertices; FP64 momenta, p^2,
+                   propagator denominators and helicity-sum accumulation */
+} me_precision;
+
+/* Standard-Model inputs.  me_default_params() fills the benchmark values
+ * alpha = 1/132.507, sin^2 thetaW = 0.2222, MZ = 91.188, GZ = 2.441,
+ * mt = 173, Gt = 1.49, alpha_s = 0.118, zero-width t-channel mode on, FP64,
+ * helicity-filter sample of 1024 events at sqrt(s) = 1500 GeV, seed 1. */
+typedef struct {
+  double alpha_em;
+  double sin2_thetaw;
+  double mz, wz;
+  double mt, wt;
+  double alpha_s;
+  int32_t tchannel_zero_width;
+  int32_t precision;        /* me_precision */
+  double filter_sqrt_s;     /* CM energy of the helicity-filter sample (GeV) */
+  uint64_t filter_seed;
+  int32_t filter_nevt;      /* number of filter events (>= 1) */
+  int32_t reserved;
+} me_sm_params;
+
+typedef struct {
+  int32_t npar;             /* external legs */
+  int32_t nhel;             /* 2^npar helicity configurations */
+  int32_t nhel_good;        /* configurations summed by me_compute */
+  int32_t ndiagrams;        /* tree-level Feynman diagrams */
+  int32_t ncolor;           /* colour flows (jamps) */
+  int32_t iden;             /* averaging and symmetry denominator */
+  int64_t flops_per_event;  /* algorithmic flops of one me_compute event */
+  int64_t bytes_per_event;  /* HBM bytes one event needs: 32 npar in + 8 out */
+  int32_t precision;
+  int32_t filtered;         /* 1 after me_helicity_filter */
+} me_info_t;
+
+/* Fill *p with the benchmark Standard-Model inputs listed above. */
+void me_default_params(me_sm_params* p);
+
+/* Create a handle for `process` (one of the strings above) with inputs *p on
+ * the current HIP device.  Copies the constants the kernels need; *out
+ * receives the handle.  ME_EPROCESS for an unknown process string. */
+me_status me_create(const char* process, const me_sm_params* p, me_handle* out);
+
+/* Helicity filtering at initialisation: evaluates |M_h|^2 for all 2^npar
+ * helicity configurations on filter_nevt RAMBO events at filter_sqrt_s
+ * (centre-of-mass frame, seed filter_seed) in FP64 and keeps configuration h
+ * iff max_events |M_h|^2 / sum_h' |M_h'|^2 > 1e-24.  Synchronous, idempotent.
+ * Without it me_compute sums all 2^npar configurations (correct, slower). */
+me_status me_helicity_filter(me_handle h);
+
+/* |M|^2 for nevt events: d_momenta [nevt][npar][4] and d_me [nevt] are device
+ * pointers, hip_stream a hipStream_t (NULL: default stream).  Asynchronous. */
+me_status me_compute(me_handle h, const double* d_momenta, int64_t nevt, double* d_me,
+                     void* hip_stream);
+
+/* Colour-summed (not averaged) |M_h|^2 of all 2^npar helicity configurations,
+ * d_me_hel [nevt][2^npar], FP64.  Diagnostic; asynchronous. */
+me_status me_compute_helicities(me_handle h, const double* d_momenta, int64_t nevt,
+                                double* d_me_hel, void* hip_stream);
+
+/* Good-helicity list after filtering: hel[0..*n) (capacity cap entries). */
+me_status me_good_helicities(me_handle h, int32_t* hel, int32_t cap, int32_t* n);
+
+/* Static data of the handle's process and current helicity selection. */
+me_status me_info(me_handle h, me_info_t* info);
+
+/* Release the handle.  No work on it may be in flight. */
+me_status me_destroy(me_handle h);
+
+/* Thread-local text of the last error (never NULL). */
+const char* me_last_error(void);
+
+/* ------------------------------------------------------------ serving --
+ * A persistent request loop for uneven |M|^2 batches of several processes,
+ * as integration channels emit them (continuous batching).  Requests are
+ * admitted in arrival order as stream slots and device memory (budget_bytes,
+ * counting each request's device momenta + output) free up; admitted work on
+ * different slots overlaps on the device.  Host buffers: the server stages
+ * momenta to device memory and results back.  Handles must be filtered
+ * before submission and stay alive while their requests are in flight.
+ */
+typedef struct me_server_s* me_server;
+
+typedef struct {
+  int64_t submitted, completed, failed, rejected;
+  int64_t events_completed;
+  int64_t bytes_in_use, peak_bytes_in_use;
+  int32_t active_slots, queued;
+} me_server_stats_t;
+
+/* n_slots HIP streams (1..64), budget_bytes of device memory for requests. */
+me_status me_server_create(int64_t budget_bytes, int32_t n_slots, me_server* out);
+
+/* Enqueue a request: h_momenta [nevt][npar][4] and h_out [nevt] are HOST
+ * pointers that must stay valid until the ticket completes.  ME_EINVAL for
+ * nevt <= 0; ME_ENOMEM if the request alone exceeds the budget.  *ticket
+ * receives an id (monotonic from 1). */
+me_status me_server_submit(me_server s, me_handle h, const double* h_momenta, int64_t nevt,
+                           double* h_out, int64_t* ticket);
+
+/* Non-blocking: *done = 1 when the ticket finished (status in *result),
+ * *latency_s = time from submit to completion seen by the server loop. */
+me_status me_server_poll(me_server s, int64_t ticket, int32_t* done, me_status* result,
+                         double* latency_s);
+
+/* Block until the ticket finished or timeout_s elapsed (ME_EBUSY then). */
+me_status me_server_wait(me_server s, int64_t ticket, double timeout_s, me_status* result,
+                         double* latency_s);
+
+me_status me_server_stats(me_server s, me_server_stats_t* st);
+
+/* Drain in-flight work, stop the loop and free all resources. */
+me_status me_server_destroy(me_server s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ME_H */

@@ -1,0 +1,316 @@
+// Device-side helicity-amplitude building blocks for gfx950 (one event per lane).
+//
+// HELAS-style functions (Murayama, Watanabe, Hagiwara, KEK-91-11) written from
+// the Feynman rules in the chiral (Weyl) representation:
+//   gamma^mu = [[0, sigma^mu], [sigmabar^mu, 0]], sigma = (1, s_k),
+//   sigmabar = (1, -s_k), gamma^5 = diag(-1, 1); components 0,1 are
+//   left-handed, 2,3 right-handed.
+// Every fermion-vector vertex is  i gamma^mu (gL P_L + gR P_R)  with real gL, gR:
+//   QCD  q qbar g : gL = gR = g_s            (rule +i g_s gamma^mu t^a)
+//   QED  f fbar a : gL = gR = -e Q
+//   Z    f fbar Z : gL = -e cL, gR = -e cR
+// Propagators: fermion i(P/+m)/(P^2-m^2+i m Gamma); gluon/photon -i g/K^2;
+// Z -i(g - K K/M^2)/(K^2-M^2+i M Gamma).  The three-gluon vertex is
+// g f^{abc} V^{mu nu rho}(k,p,q), the four-gluon vertex -i g^2 (f f)(g g - g g);
+// colour factors are handled outside these functions.
+//
+// Wavefunctions: column spinors (u for incoming fermions, v for outgoing
+// antifermions), row spinors (ubar for outgoing fermions, vbar for incoming
+// antifermions; stored so that rowspinor.col = sum_i r_i c_i) and vectors
+// with upper Lorentz index.  Momenta K are the momentum that the current
+// carries into the vertex it feeds; P along the fermion-number arrow.
+//
+// T is the arithmetic type of the wavefunction algebra (double for the FP64
+// form, float for the mixed form).  Momenta, p^2 and propagator denominators
+// are always formed in double by the caller and rounded to T there.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace me {
+
+template <class T> struct cx { T r, i; };
+
+template <class T> __device__ __forceinline__ cx<T> mk(T r, T i) { return cx<T>{r, i}; }
+template <class T> __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.r + b.r, a.i + b.i}; }
+template <class T> __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.r - b.r, a.i - b.i}; }
+template <class T> __device__ __forceinline__ cx<T> operator-(cx<T> a) { return {-a.r, -a.i}; }
+template <class T> __device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b) {
+  return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r};
+}
+template <class T> __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return {s * a.r, s * a.i}; }
+template <class T> __device__ __forceinline__ cx<T> operator*(cx<T> a, T s) { return {s * a.r, s * a.i}; }
+template <class T> __device__ __forceinline__ cx<T> mul_i(cx<T> a) { return {-a.i, a.r}; }      // i a
+template <class T> __device__ __forceinline__ cx<T> mul_mi(cx<T> a) { return {a.i, -a.r}; }     // -i a
+template <class T> __device__ __forceinline__ cx<T> cconj(cx<T> a) { return {a.r, -a.i}; }
+// a*b + c
+template <class T> __device__ __forceinline__ cx<T> cfma(cx<T> a, cx<T> b, cx<T> c) {
+  return {a.r * b.r - a.i * b.i + c.r, a.r * b.i + a.i * b.r + c.i};
+}
+
+template <class T> struct wf { cx<T> c[4]; };   // spinor or vector wavefunction
+template <class T> struct mom { T k[4]; };      // real momentum in arithmetic type T
+
+template <class T> __device__ __forceinline__ mom<T> to_mom(const double* K) {
+  return mom<T>{{T(K[0]), T(K[1]), T(K[2]), T(K[3])}};
+}
+__device__ __forceinline__ double msq(const double* K) {
+  return K[0] * K[0] - K[1] * K[1] - K[2] * K[2] - K[3] * K[3];
+}
+
+// Minkowski product of complex 4-vectors (no conjugation).
+template <class T> __device__ __forceinline__ cx<T> dot(const wf<T>& a, const wf<T>& b) {
+  cx<T> s = a.c[0] * b.c[0];
+  s = s - a.c[1] * b.c[1];
+  s = s - a.c[2] * b.c[2];
+  s = s - a.c[3] * b.c[3];
+  return s;
+}
+// Minkowski product of a real momentum with a complex vector.
+template <class T> __device__ __forceinline__ cx<T> dot(const mom<T>& k, const wf<T>& b) {
+  return cx<T>{k.k[0] * b.c[0].r - k.k[1] * b.c[1].r - k.k[2] * b.c[2].r - k.k[3] * b.c[3].r,
+               k.k[0] * b.c[0].i - k.k[1] * b.c[1].i - k.k[2] * b.c[2].i - k.k[3] * b.c[3].i};
+}
+
+// ------------------------------------------------------- external states
+// Two-component helicity eigenstates chi_+/- of sigma.p_hat, computed in FP64.
+// |p|+p_z is formed as p_T^2/(|p|-p_z) for p_z < 0 to avoid cancellation; on
+// the negative z axis chi_+ = (0,1), chi_- = (-1,0).
+struct chi2 { double ar, ai, br, bi; };
+__device__ __forceinline__ void helicity_chis(const double* p, chi2& cp, chi2& cm) {
+  const double pt2 = p[1] * p[1] + p[2] * p[2];
+  const double pp = sqrt(pt2 + p[3] * p[3]);
+  const double a = p[3] >= 0 ? pp + p[3] : (pt2 > 0 ? pt2 / (pp - p[3]) : 0.0);
+  if (a > 0) {
+    const double n = 1.0 / sqrt(2.0 * pp * a);
+    cp = chi2{a * n, 0.0, p[1] * n, p[2] * n};
+    cm = chi2{-p[1] * n, p[2] * n, a * n, 0.0};
+  } else {
+    cp = chi2{0.0, 0.0, 1.0, 0.0};
+    cm = chi2{-1.0, 0.0, 0.0, 0.0};
+  }
+}
+// sqrt(E -+ |p|), sqrt(E + |p|): omega_- is taken as m/omega_+ (exactly 0 when massless).
+__device__ __forceinline__ void omegas(const double* p, double m, double& wp, double& wm) {
+  const double pp = sqrt(p[1] * p[1] + p[2] * p[2] + p[3] * p[3]);
+  wp = sqrt(p[0] + pp);
+  wm = m == 0.0 ? 0.0 : m / wp;
+}
+template <class T> __device__ __forceinline__ cx<T> c2(double r, double i) { return cx<T>{T(r), T(i)}; }
+
+// u(p,lam) = (omega_{-lam} chi_lam ; omega_lam chi_lam)   (column)
+template <class T> __device__ __forceinline__ wf<T> ext_u(const double* p, double m, int lam) {
+  chi2 cp, cm; helicity_chis(p, cp, cm);
+  double wp, wm; omegas(p, m, wp, wm);
+  const chi2 x = lam > 0 ? cp : cm;
+  const double lo = lam > 0 ? wm : wp, hi = lam > 0 ? wp : wm;
+  wf<T> w;
+  w.c[0] = c2<T>(lo * x.ar, lo * x.ai); w.c[1] = c2<T>(lo * x.br, lo * x.bi);
+  w.c[2] = c2<T>(hi * x.ar, hi * x.ai); w.c[3] = c2<T>(hi * x.br, hi * x.bi);
+  return w;
+}
+// v(p,lam) = (-lam omega_lam chi_{-lam} ; lam omega_{-lam} chi_{-lam})   (column)
+template <class T> __device__ __forceinline__ wf<T> ext_v(const double* p, double m, int lam) {
+  chi2 cp, cm; helicity_chis(p, cp, cm);
+  double wp, wm; omegas(p, m, wp, wm);
+  const chi2 x = lam > 0 ? cm : cp;
+  const double up = lam > 0 ? -wp : wm;         // -lam omega_lam
+  const double dn = lam > 0 ? wm : -wp;         // lam omega_{-lam}
+  wf<T> w;
+  w.c[0] = c2<T>(up * x.ar, up * x.ai); w.c[1] = c2<T>(up * x.br, up * x.bi);
+  w.c[2] = c2<T>(dn * x.ar, dn * x.ai); w.c[3] = c2<T>(dn * x.br, dn * x.bi);
+  return w;
+}
+// Dirac adjoint psi^dagger gamma^0 as a row: (conj psi_R, conj psi_L).
+template <class T> __device__ __forceinline__ wf<T> bar(const wf<T>& s) {
+  wf<T> r;
+  r.c[0] = cconj(s.c[2]); r.c[1] = cconj(s.c[3]);
+  r.c[2] = cconj(s.c[0]); r.c[3] = cconj(s.c[1]);
+  return r;
+}
+// Massless vector polarisation eps(k,lam) = (-lam e1 - i e2)/sqrt2,
+// e1 = (0, cos th cos ph, cos th sin ph, -sin th), e2 = (0, -sin ph, cos ph, 0);
+// phi = 0 on the z axis.  conj_out selects eps* (outgoing vectors).
+template <class T> __device__ __forceinline__ wf<T> ext_eps(const double* k, int lam, bool conj_out) {
+  const double pt2 = k[1] * k[1] + k[2] * k[2];
+  const double pt = sqrt(pt2);
+  const double kk = sqrt(pt2 + k[3] * k[3]);
+  double cph = 1.0, sph = 0.0, cth, sth;
+  if (pt > 0) { cph = k[1] / pt; sph = k[2] / pt; cth = k[3] / kk; sth = pt / kk; }
+  else { cth = k[3] >= 0 ? 1.0 : -1.0; sth = 0.0; }
+  const double r2 = 0.70710678118654752440;
+  const double l = double(lam);
+  const double s = conj_out ? -1.0 : 1.0;
+  wf<T> e;
+  e.c[0] = c2<T>(0.0, 0.0);
+  e.c[1] = c2<T>(-l * cth * cph * r2, s * sph * r2);
+  e.c[2] = c2<T>(-l * cth * sph * r2, -s * cph * r2);
+  e.c[3] = c2<T>(l * sth * r2, 0.0);
+  return e;
+}
+
+// --------------------------------------------------- fermion-vector vertex
+// Components of J.sigma = [[b, -d], [-c, a]] and J.sigmabar = [[a, d], [c, b]],
+// a = J0+J3, b = J0-J3, c = J1 + i J2, d = J1 - i J2.
+template <class T> struct jsig { cx<T> a, b, c, d; };
+template <class T> __device__ __forceinline__ jsig<T> sig(const wf<T>& J) {
+  jsig<T> s;
+  s.a = J.c[0] + J.c[3];
+  s.b = J.c[0] - J.c[3];
+  s.c = J.c[1] + mul_i(J.c[2]);
+  s.d = J.c[1] - mul_i(J.c[2]);
+  return s;
+}
+
+// Amplitude  rbar [i gamma.J (gL P_L + gR P_R)] psi.
+template <class T>
+__device__ __forceinline__ cx<T> ffv_amp(const wf<T>& r, const wf<T>& J, const wf<T>& s, T gL, T gR) {
+  const jsig<T> q = sig(J);
+  // r_L (J.sigma) psi_R
+  cx<T> x = r.c[0] * (q.b * s.c[2] - q.d * s.c[3]) + r.c[1] * (q.a * s.c[3] - q.c * s.c[2]);
+  // r_R (J.sigmabar) psi_L
+  cx<T> y = r.c[2] * (q.a * s.c[0] + q.d * s.c[1]) + r.c[3] * (q.c * s.c[0] + q.b * s.c[1]);
+  return mul_i(gR * x + gL * y);
+}
+
+// Off-shell column spinor  i(K/+m)/(K^2-m^2+i m G) [i gamma.J (gL P_L+gR P_R)] psi.
+// K: momentum along the arrow (into the next vertex); den = 1/(K^2-m^2+i m G).
+template <class T>
+__device__ __forceinline__ wf<T> ffv_fin(const wf<T>& s, const wf<T>& J, const mom<T>& K, T m, cx<T> den,
+                                         T gL, T gR) {
+  const jsig<T> q = sig(J);
+  const cx<T> x0 = gR * (q.b * s.c[2] - q.d * s.c[3]);
+  const cx<T> x1 = gR * (q.a * s.c[3] - q.c * s.c[2]);
+  const cx<T> x2 = gL * (q.a * s.c[0] + q.d * s.c[1]);
+  const cx<T> x3 = gL * (q.c * s.c[0] + q.b * s.c[1]);
+  const T kp = K.k[0] + K.k[3], km = K.k[0] - K.k[3];
+  const cx<T> kc{K.k[1], K.k[2]}, kd{K.k[1], -K.k[2]};   // K1 + i K2, K1 - i K2
+  const cx<T> nd = -den;                                 // i * i * den
+  wf<T> o;
+  o.c[0] = nd * (km * x2 - kd * x3 + m * x0);
+  o.c[1] = nd * (kp * x3 - kc * x2 + m * x1);
+  o.c[2] = nd * (kp * x0 + kd * x1 + m * x2);
+  o.c[3] = nd * (kc * x0 + km * x1 + m * x3);
+  return o;
+}
+
+// Off-shell row spinor  rbar [i gamma.J (gL P_L+gR P_R)] i(P/+m)/(P^2-m^2+i m G).
+// P: momentum along the arrow (= minus the momentum the row current carries
+// into its next vertex).
+template <class T>
+__device__ __forceinline__ wf<T> ffv_fout(const wf<T>& r, const wf<T>& J, const mom<T>& P, T m, cx<T> den,
+                                          T gL, T gR) {
+  const jsig<T> q = sig(J);
+  const cx<T> s0 = gL * (r.c[2] * q.a + r.c[3] * q.c);
+  const cx<T> s1 = gL * (r.c[2] * q.d + r.c[3] * q.b);
+  const cx<T> s2 = gR * (r.c[0] * q.b - r.c[1] * q.c);
+  const cx<T> s3 = gR * (r.c[1] * q.a - r.c[0] * q.d);
+  const T kp = P.k[0] + P.k[3], km = P.k[0] - P.k[3];
+  const cx<T> kc{P.k[1], P.k[2]}, kd{P.k[1], -P.k[2]};
+  const cx<T> nd = -den;
+  wf<T> o;
+  // (s_L, s_R) [[m, P.sigma], [P.sigmabar, m]]
+  o.c[0] = nd * (m * s0 + kp * s2 + kc * s3);
+  o.c[1] = nd * (m * s1 + kd * s2 + km * s3);
+  o.c[2] = nd * (km * s0 - kc * s1 + m * s2);
+  o.c[3] = nd * (kp * s1 - kd * s0 + m * s3);
+  return o;
+}
+
+// Fermion current  j^mu = rbar gamma^mu (gL P_L + gR P_R) psi  (no factor i).
+template <class T>
+__device__ __forceinline__ wf<T> ffv_current(const wf<T>& r, const wf<T>& s, T gL, T gR) {
+  // r_R sigmabar^mu psi_L
+  const cx<T> l0 = r.c[2] * s.c[0] + r.c[3] * s.c[1];
+  const cx<T> l1 = -(r.c[2] * s.c[1] + r.c[3] * s.c[0]);
+  const cx<T> l2 = mul_i(r.c[2] * s.c[1] - r.c[3] * s.c[0]);
+  const cx<T> l3 = r.c[3] * s.c[1] - r.c[2] * s.c[0];
+  // r_L sigma^mu psi_R
+  const cx<T> h0 = r.c[0] * s.c[2] + r.c[1] * s.c[3];
+  const cx<T> h1 = r.c[0] * s.c[3] + r.c[1] * s.c[2];
+  const cx<T> h2 = mul_i(r.c[1] * s.c[2] - r.c[0] * s.c[3]);
+  const cx<T> h3 = r.c[0] * s.c[2] - r.c[1] * s.c[3];
+  wf<T> j;
+  j.c[0] = gL * l0 + gR * h0;
+  j.c[1] = gL * l1 + gR * h1;
+  j.c[2] = gL * l2 + gR * h2;
+  j.c[3] = gL * l3 + gR * h3;
+  return j;
+}
+// Off-shell massless vector (gluon, photon): (-i/K^2) (i j^mu) = j^mu / K^2.
+template <class T>
+__device__ __forceinline__ wf<T> ffv_v0(const wf<T>& r, const wf<T>& s, T inv_k2, T gL, T gR) {
+  wf<T> j = ffv_current(r, s, gL, gR);
+  for (int m = 0; m < 4; ++m) j.c[m] = inv_k2 * j.c[m];
+  return j;
+}
+// Off-shell massive vector, unitary gauge: den [j^mu - K^mu (K.j)/M^2].
+template <class T>
+__device__ __forceinline__ wf<T> ffv_vm(const wf<T>& r, const wf<T>& s, const mom<T>& K, T inv_m2, cx<T> den,
+                                        T gL, T gR) {
+  wf<T> j = ffv_current(r, s, gL, gR);
+  const cx<T> kj = dot(K, j) * inv_m2;
+  wf<T> o;
+  for (int m = 0; m < 4; ++m) o.c[m] = den * (j.c[m] - K.k[m] * kj);
+  return o;
+}
+
+// ---------------------------------------------------------- gluon vertices
+// V^mu(A,B) = A^mu ((k-p).B) + (A.B)(p-q)^mu + B^mu ((q-k).A) with incoming
+// momenta p = KA, q = KB and k = -(KA+KB) on the free leg.
+template <class T>
+__device__ __forceinline__ wf<T> vvv_lorentz(const wf<T>& A, const mom<T>& KA, const wf<T>& B, const mom<T>& KB) {
+  mom<T> kmp, pmq, qmk;
+  for (int m = 0; m < 4; ++m) {
+    kmp.k[m] = -T(2) * KA.k[m] - KB.k[m];
+    pmq.k[m] = KA.k[m] - KB.k[m];
+    qmk.k[m] = T(2) * KB.k[m] + KA.k[m];
+  }
+  const cx<T> t1 = dot(kmp, B), t2 = dot(A, B), t3 = dot(qmk, A);
+  wf<T> v;
+  for (int m = 0; m < 4; ++m) v.c[m] = A.c[m] * t1 + B.c[m] * t3 + pmq.k[m] * t2;
+  return v;
+}
+// Off-shell gluon from a three-gluon vertex: (-i/K^2) g V^mu(A,B).
+template <class T>
+__device__ __forceinline__ wf<T> vvv_v(const wf<T>& A, const mom<T>& KA, const wf<T>& B, const mom<T>& KB,
+                                       T g_inv_k2) {
+  wf<T> v = vvv_lorentz(A, KA, B, KB);
+  for (int m = 0; m < 4; ++m) v.c[m] = mul_mi(g_inv_k2 * v.c[m]);
+  return v;
+}
+// Amplitude  g V^{mu nu rho}(k,p,q) X_mu A_nu B_rho with incoming momenta
+// k = KX, p = KA, q = KB (KX + KA + KB = 0).
+template <class T>
+__device__ __forceinline__ cx<T> vvv_amp(const wf<T>& X, const mom<T>& KX, const wf<T>& A, const mom<T>& KA,
+                                         const wf<T>& B, const mom<T>& KB, T g) {
+  mom<T> kmp, pmq, qmk;
+  for (int m = 0; m < 4; ++m) {
+    kmp.k[m] = KX.k[m] - KA.k[m];
+    pmq.k[m] = KA.k[m] - KB.k[m];
+    qmk.k[m] = KB.k[m] - KX.k[m];
+  }
+  const cx<T> r = dot(X, A) * dot(kmp, B) + dot(A, B) * dot(pmq, X) + dot(B, X) * dot(qmk, A);
+  return g * r;
+}
+// Four-gluon piece for the colour structure f^{x b e} f^{e c d}:
+// P^mu(b; c, d) = C^mu (B.D) - D^mu (B.C).
+template <class T>
+__device__ __forceinline__ wf<T> vvvv_piece(const wf<T>& B, const wf<T>& C, const wf<T>& D) {
+  const cx<T> bd = dot(B, D), bc = dot(B, C);
+  wf<T> v;
+  for (int m = 0; m < 4; ++m) v.c[m] = C.c[m] * bd - D.c[m] * bc;
+  return v;
+}
+// Identity that the compiler cannot see through: a recomputed wavefunction
+// passes one input through it so that it is not merged with the first copy.
+template <class T> __device__ __forceinline__ wf<T> opaque(wf<T> w) {
+#pragma unroll
+  for (int m = 0; m < 4; ++m) asm volatile("" : "+v"(w.c[m].r), "+v"(w.c[m].i));
+  return w;
+}
+template <class T> __device__ __forceinline__ void acc_scaled(wf<T>& o, const wf<T>& v, T s) {
+  for (int m = 0; m < 4; ++m) o.c[m] = o.c[m] + s * v.c[m];
+}
+
+}  // namespace me

@@ -1,0 +1,83 @@
+// Event-parallel |M|^2 kernels for gfx950: one event per lane, the helicity
+// loop inside the lane (uniform across the wave, no divergence), the colour
+// sum and the helicity sum fused in the same kernel so that only the momenta
+// are read from and one double per event is written to HBM.
+//
+// Per process the generator supplies  struct Proc { NPAR, NCOLOR, NHEL, CDEN,
+// IDEN, amplitudes<T>(), colour_sum<T>() }.  T = double is the FP64 form;
+// T = float is the mixed form (FP32 wavefunctions and vertices, FP64
+// momenta, p^2, propagator denominators and helicity-sum accumulation).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "helas.hpp"
+#include "me_types.h"
+
+namespace me {
+
+template <class T> __device__ __forceinline__ mom<T> neg(const mom<T>& k) {
+  return mom<T>{{-k.k[0], -k.k[1], -k.k[2], -k.k[3]}};
+}
+// 1/(K^2 - m^2 + i m w), formed in FP64 and rounded to T.
+template <class T> __device__ __forceinline__ cx<T> prop_den(const double* K, double m, double w) {
+  const double a = msq(K) - m * m, b = m * w;
+  const double r = 1.0 / (a * a + b * b);
+  return cx<T>{T(a * r), T(-b * r)};
+}
+
+template <class P, class T>
+__global__ __launch_bounds__(256) void me_kernel(const double* __restrict__ mom, int64_t nevt,
+                                                 double* __restrict__ out, double* __restrict__ out_hel,
+                                                 const MeParams prm) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= nevt) return;
+  double p[P::NPAR][4];
+  const double2* src = reinterpret_cast<const double2*>(mom + e * (4 * P::NPAR));
+#pragma unroll
+  for (int i = 0; i < P::NPAR; ++i) {
+    const double2 a = src[2 * i], b = src[2 * i + 1];
+    p[i][0] = a.x; p[i][1] = a.y; p[i][2] = b.x; p[i][3] = b.y;
+  }
+  double acc = 0.0;
+  for (int ih = 0; ih < prm.nhel; ++ih) {
+    // Momentum sums and propagator factors are recomputed per helicity where
+    // they are used; hiding p from loop-invariant code motion keeps the
+    // compiler from hoisting them all and holding them in registers.
+#pragma unroll
+    for (int i = 0; i < P::NPAR; ++i)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) asm volatile("" : "+v"(p[i][c]));
+    const unsigned hel = prm.hel[ih];
+    cx<T> jamp[P::NCOLOR];
+    P::template amplitudes<T>(p, hel, prm, jamp);
+    const double q = double(P::template colour_sum<T>(jamp));
+    if (out_hel) out_hel[e * P::NHEL + hel] = q * (1.0 / P::CDEN);
+    acc += q;
+  }
+  if (out) out[e] = acc * (1.0 / (P::CDEN * P::IDEN));
+}
+
+// mode: ME_MODE_FP64 or ME_MODE_MIXED.  out_hel (FP64 only) receives the
+// colour-summed |M_h|^2 of every listed helicity, [nevt][NHEL].
+template <class P>
+int launch(int mode, const double* mom, int64_t nevt, double* out, double* out_hel, const MeParams& prm,
+           hipStream_t stream) {
+  if (nevt <= 0) return 0;
+  const int block = 256;
+  const int64_t nblk = (nevt + block - 1) / block;
+  if (nblk > 0x7fffffffLL) return -1;
+  if (mode == ME_MODE_FP64) {
+    hipLaunchKernelGGL((me_kernel<P, double>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
+                       out_hel, prm);
+  } else if (mode == ME_MODE_MIXED) {
+    if (out_hel) return -1;
+    hipLaunchKernelGGL((me_kernel<P, float>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
+                       nullptr, prm);
+  } else {
+    return -1;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+}  // namespace me

@@ -1,0 +1,36 @@
+// Types shared by the runtime and the generated kernels (internal; the public
+// interface is include/me.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace me {
+
+enum { ME_MODE_FP64 = 0, ME_MODE_MIXED = 1 };
+
+// Kernel argument block (passed by value; lives in the kernarg segment).
+struct MeParams {
+  double gs;        // strong coupling g_s = sqrt(4 pi alpha_s)
+  double ea;        // photon-fermion coupling -e Q (Q = -1 for the leptons)
+  double gzl, gzr;  // Z-lepton couplings -e cL, -e cR
+  double mz, wz;    // Z mass and width
+  double mt, wt;    // top mass and width (s-channel propagators)
+  double wt_tchan;  // top width in t-channel propagators (0 in zero-width mode)
+  int32_t nhel;     // number of helicity configurations in hel[]
+  int32_t pad;
+  uint8_t hel[128]; // helicity configurations: bit i = leg i has helicity +1
+};
+
+typedef int (*LaunchFn)(int mode, const double* mom, int64_t nevt, double* out, double* out_hel,
+                        const MeParams* prm, hipStream_t stream);
+
+struct ProcessEntry {
+  const char* name;
+  const char* process;
+  int npar, ncolor, nhel, ndiagrams, iden, colour_den;
+  long flops_per_hel;  // algorithmic flops of one helicity of one event
+  int massive_top;     // legs 2 and 3 carry the top mass
+  LaunchFn launch;
+};
+
+}  // namespace me

@@ -1,0 +1,64 @@
+"""PyTorch convenience layer over the C ABI: device tensors in, device tensors
+out.  PyTorch provides device memory and streams only; every step of the
+matrix-element evaluation runs in the HIP kernels behind ``binding``."""
+from __future__ import annotations
+
+import torch
+
+from . import binding as B
+
+PROCESS_NAMES = {
+    "eemumu": "e+ e- > mu+ mu-",
+    "ggtt": "g g > t t~",
+    "ggttg": "g g > t t~ g",
+    "ggttgg": "g g > t t~ g g",
+}
+
+
+class MatrixElement:
+    """One process handle.  precision: "fp64" or "mixed"."""
+
+    def __init__(self, process: str, precision: str = "fp64", filter_helicities: bool = True, **params):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the matrix-element engine has no CPU path")
+        prm = B.me_default_params(**params)
+        prm.precision = {"fp64": B.ME_FP64, "mixed": B.ME_MIXED}[precision]
+        self.process = PROCESS_NAMES.get(process, process)
+        self.handle = B.me_create(self.process, prm)
+        if filter_helicities:
+            B.me_helicity_filter(self.handle)
+        self.info = B.me_info(self.handle)
+
+    def __call__(self, momenta: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        if momenta.dtype != torch.float64 or not momenta.is_cuda or not momenta.is_contiguous():
+            raise ValueError("momenta must be a contiguous float64 CUDA tensor [nevt][npar][4]")
+        if momenta.dim() != 3 or momenta.shape[1] != self.info["npar"] or momenta.shape[2] != 4:
+            raise ValueError(f"momenta must have shape [nevt][{self.info['npar']}][4]")
+        n = momenta.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=momenta.device)
+        elif out.dtype != torch.float64 or not out.is_cuda or not out.is_contiguous() or out.numel() < n:
+            raise ValueError("out must be a contiguous float64 CUDA tensor with nevt elements")
+        B.me_compute(self.handle, momenta.data_ptr(), n, out.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        return out
+
+    def helicities(self, momenta: torch.Tensor) -> torch.Tensor:
+        n = momenta.shape[0]
+        out = torch.empty((n, self.info["nhel"]), dtype=torch.float64, device=momenta.device)
+        B.me_compute_helicities(self.handle, momenta.data_ptr(), n, out.data_ptr(),
+                                torch.cuda.current_stream().cuda_stream)
+        return out
+
+    def good_helicities(self):
+        return B.me_good_helicities(self.handle)
+
+    def close(self):
+        if self.handle:
+            B.me_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

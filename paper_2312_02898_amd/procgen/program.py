@@ -1,0 +1,454 @@
+"""Process compiler: straight-line helicity-amplitude programs (build time).
+
+A program is the list of HELAS-style vertex calls that evaluates, for one
+event and one helicity configuration, every Feynman diagram of a process and
+accumulates the colour-flow amplitudes jamp_k (the matrix-element evaluation
+that the paper offloads, Sec. 2 and Sec. 3).  Sub-diagrams are computed once
+and shared between all diagrams that contain them.
+
+Conventions
+  * legs in the order of the process string; legs 0 and 1 incoming.  The
+    momentum a leg carries INTO the diagram is k_i = +p_i (incoming) or -p_i
+    (outgoing); an internal line fed by the legs in mask S carries
+    K_S = sum_{i in S} k_i into the vertex it feeds.
+  * helicity configuration h: leg i has helicity +1 iff bit i of h is set.
+  * the top line runs from the outgoing top (row spinor ubar) to the outgoing
+    antitop (column spinor v).  A diagram of t tbar + n gluons is an ordered
+    sequence of gluon trees T1..Tk hanging off that line (top side first).
+  * gluon trees are canonical binary trees (children ordered by smallest
+    leaf).  The four-gluon vertex never needs a tree of its own: each of its
+    three colour structures f^{xbe} f^{ecd} has the colour of the binary tree
+    (b, (c, d)) and is added to that tree's current.
+  * a propagator is "t-channel" when its mask holds exactly one incoming leg;
+    the top width used there is a run-time parameter (zero in the paper's
+    zero-width t-channel mode, Sec. 3).
+
+The builder produces a DAG (values = wavefunctions, items = amplitudes with
+their jamp updates).  ``schedule`` turns it into straight-line code for one
+lane: amplitudes in a locality-friendly order, every wavefunction computed
+just before it is needed and kept in a cache of at most ``budget``
+wavefunctions; when the cache is full the value whose next use is furthest
+away is dropped and recomputed later (Belady's rule).  That bounds the
+registers a lane needs at the cost of some recomputation.
+"""
+from __future__ import annotations
+
+import itertools
+from dataclasses import dataclass, field
+from functools import lru_cache
+
+from . import colour
+
+# Static flop counts of the device functions (add/mul = 1, FMA = 2, complex
+# mul = 6, complex add = 2, real*complex = 2), used for the algorithmic flop
+# count of a helicity.  sqrt and division are counted as 1 each.
+FLOPS = {
+    "ext_u": 40, "ext_v": 40, "ext_ubar": 40, "ext_vbar": 40, "ext_eps": 30,
+    "ffv_fin": 154, "ffv_fout": 154, "ffv_v0": 144, "ffv_vm": 170,
+    "vvv_v": 158, "vvvv_acc": 132,
+    "amp_ffv": 98, "amp_vvv": 168, "amp_vvvv_acc": 150,
+    "ffv_v0_ew": 144, "ffv_vm_ew": 170, "amp_ffv_ew": 98, "amp_ffv_ew_acc": 100,
+}
+# momentum sum per extra leg, and the propagator factor per kind
+DEN_FLOPS = {"top_t": 12, "top_s": 12, "gluon": 8, "z": 12, "photon": 8}
+
+
+@dataclass
+class Op:
+    kind: str
+    out: str | None          # value written (None for jamp updates)
+    ins: list                # value names read
+    prm: dict = field(default_factory=dict)
+
+
+@dataclass
+class Program:
+    name: str
+    process: str
+    npar: int
+    leg_sign: list            # +1 incoming, -1 outgoing
+    ncolor: int
+    colour_num: list          # integer colour matrix
+    colour_den: int
+    iden: int
+    n_diagrams: int
+    values: dict = field(default_factory=dict)   # name -> list[Op] defining it
+    deps: dict = field(default_factory=dict)     # name -> list of value names
+    items: list = field(default_factory=list)    # (list[Op] amplitude ops + jamp op, deps)
+    dens: dict = field(default_factory=dict)     # mask -> propagator kind
+    ops: list = field(default_factory=list)      # scheduled straight-line code
+
+    def value_masks(self, op: Op):
+        return [v for k, v in op.prm.items() if k.startswith("m")]
+
+    def flops_of(self, ops) -> int:
+        f = 0
+        for op in ops:
+            if op.kind == "jamp":
+                f += 2 * len(op.prm["jam"])
+            else:
+                f += FLOPS.get(op.kind, 0)
+        return f
+
+    def flops_per_helicity(self) -> int:
+        """Algorithmic flops of one helicity: every distinct vertex call once
+        (no recomputation), propagator factors, jamp updates, colour form."""
+        f = 0
+        for ops in self.values.values():
+            f += self.flops_of(ops)
+        for ops, _ in self.items:
+            f += self.flops_of(ops)
+        for m, kind in self.dens.items():
+            f += 4 * (bin(m).count("1") - 1) + DEN_FLOPS[kind]
+        n = self.ncolor
+        f += 2 * n * (n + 1) + 4 * n
+        return f
+
+    def executed_flops_per_helicity(self) -> int:
+        """Flops of the scheduled code including recomputation."""
+        f = self.flops_of(self.ops)
+        for m, kind in self.dens.items():
+            f += 4 * (bin(m).count("1") - 1) + DEN_FLOPS[kind]
+        n = self.ncolor
+        return f + 2 * n * (n + 1) + 4 * n
+
+    def counts(self) -> dict:
+        c = {}
+        for op in self.ops:
+            c[op.kind] = c.get(op.kind, 0) + 1
+        return c
+
+
+def _incoming_count(mask):
+    return (mask & 1) + ((mask >> 1) & 1)
+
+
+# ------------------------------------------------------------------ QCD
+def feynman_diagram_count(ng: int) -> int:
+    """Tree diagrams of g g > t t~ + (ng-2) g with 3- and 4-gluon vertices:
+    a top line carrying an ordered sequence of gluon subtrees."""
+    from math import comb
+
+    @lru_cache(maxsize=None)
+    def D(k):   # sub-diagrams of a k-gluon subtree hanging off one line
+        if k == 1:
+            return 1
+        tot = 0
+        for a in range(1, k):                      # binary: A holds gluon 1
+            tot += comb(k - 1, a - 1) * D(a) * D(k - a)
+        for a in range(1, k - 1):                  # ternary: A holds gluon 1,
+            for b in range(1, k - a):              # B the smallest of the rest
+                c = k - a - b
+                tot += comb(k - 1, a - 1) * comb(k - a - 1, b - 1) * D(a) * D(b) * D(c)
+        return tot
+
+    @lru_cache(maxsize=None)
+    def L(k):   # ordered sequences of subtrees covering k labelled gluons
+        if k == 0:
+            return 1
+        return sum(comb(k, a) * D(a) * L(k - a) for a in range(1, k + 1))
+    return L(ng)
+
+
+@lru_cache(maxsize=None)
+def _trees(S):
+    """Canonical binary trees over a sorted tuple of gluon labels."""
+    if len(S) == 1:
+        return (S[0],)
+    first, rest = S[0], S[1:]
+    out = []
+    for r in range(len(rest)):
+        for extra in itertools.combinations(rest, r):
+            A = (first,) + extra
+            B = tuple(x for x in rest if x not in extra)
+            for ta in _trees(A):
+                for tb in _trees(B):
+                    out.append((ta, tb))
+    return tuple(out)
+
+
+def _ordered_partitions(S):
+    if not S:
+        yield ()
+        return
+    for r in range(1, len(S) + 1):
+        for block in itertools.combinations(S, r):
+            rest = tuple(x for x in S if x not in block)
+            for tail in _ordered_partitions(rest):
+                yield (block,) + tail
+
+
+def qcd_program(ng: int) -> Program:
+    """g g > t t~ + (ng-2) g.  Gluon g sits on leg 0, 1, 4, 5, ... ."""
+    gl = [0, 1] + [4 + i for i in range(ng - 2)]
+    T, TB = 2, 3
+    npar = ng + 2
+    name = {2: "ggtt", 3: "ggttg", 4: "ggttgg", 5: "ggttggg"}[ng]
+    order = colour.basis(ng)
+    index = {s: i for i, s in enumerate(order)}
+    cnum, cden = colour.colour_matrix(ng)
+    iden = 256
+    for k in range(2, ng - 2 + 1):
+        iden *= k
+    prog = Program(name=name, process="g g > t t~" + " g" * (ng - 2), npar=npar,
+                   leg_sign=[1, 1] + [-1] * (npar - 2), ncolor=len(order), colour_num=cnum,
+                   colour_den=cden, iden=iden, n_diagrams=feynman_diagram_count(ng))
+
+    def define(name, ops):
+        prog.values[name] = ops
+        deps = []
+        for op in ops:
+            for v in op.ins:
+                if v != name and v not in deps:
+                    deps.append(v)
+        prog.deps[name] = deps
+        return name
+
+    def gmask(tree):
+        m = 0
+        for g in colour.leaves(tree):
+            m |= 1 << gl[g]
+        return m
+
+    ext = {}
+    for g in range(ng):
+        leg = gl[g]
+        ext[g] = define(f"w{leg}", [Op("ext_eps", f"w{leg}", [], {"leg": leg, "conj": leg >= 2})])
+    define("wT", [Op("ext_ubar", "wT", [], {"leg": T})])
+    define("wTB", [Op("ext_v", "wTB", [], {"leg": TB})])
+
+    tree_name = {}
+
+    def tree(t):
+        if isinstance(t, int):
+            return ext[t]
+        if t in tree_name:
+            return tree_name[t]
+        A, B = t
+        na, nb = tree(A), tree(B)
+        out = f"J{len(tree_name)}"
+        tree_name[t] = out
+        m = gmask(t)
+        prog.dens[m] = "gluon"
+        ops = [Op("vvv_v", out, [na, nb], {"mA": gmask(A), "mB": gmask(B), "m": m})]
+        if not isinstance(B, int):      # f^{x A e} f^{e B0 B1}
+            ops.append(Op("vvvv_acc", out, [out, tree(A), tree(B[0]), tree(B[1])], {"sgn": 1, "m": m}))
+        if not isinstance(A, int):      # tree (A, B) = -(B, A): f^{x B e} f^{e A0 A1}
+            ops.append(Op("vvvv_acc", out, [out, tree(B), tree(A[0]), tree(A[1])], {"sgn": -1, "m": m}))
+        return define(out, ops)
+
+    def top_mask(m):
+        prog.dens[m] = "top_t" if _incoming_count(m) == 1 else "top_s"
+        return m
+
+    rows, cols = {(): "wT"}, {(): "wTB"}
+
+    def row(prefix):
+        if prefix in rows:
+            return rows[prefix]
+        r_in, J = row(prefix[:-1]), tree(prefix[-1])
+        m = 1 << T
+        for t in prefix:
+            m |= gmask(t)
+        out = f"R{len(rows)}"
+        rows[prefix] = out
+        return define(out, [Op("ffv_fout", out, [r_in, J], {"m": top_mask(m)})])
+
+    def col(suffix):
+        if suffix in cols:
+            return cols[suffix]
+        c_in, J = col(suffix[1:]), tree(suffix[0])
+        m = 1 << TB
+        for t in suffix:
+            m |= gmask(t)
+        out = f"C{len(cols)}"
+        cols[suffix] = out
+        return define(out, [Op("ffv_fin", out, [c_in, J], {"m": top_mask(m)})])
+
+    sequences = []
+    for part in _ordered_partitions(tuple(range(ng))):
+        for trees in itertools.product(*[_trees(b) for b in part]):
+            sequences.append(trees)
+
+    def new_currents(seq, j):
+        n = sum(1 for m in range(1, j) if seq[:m] not in rows)
+        return n + sum(1 for m in range(j, len(seq)) if seq[m:] not in cols)
+
+    mtt = (1 << T) | (1 << TB)
+    namp = 0
+    # longest sequences first: they fix the shared row/column currents
+    for seq in sorted(sequences, key=lambda s: -len(s)):
+        coeffs = colour.expand_line(seq)
+        jam = [(index[s], c) for s, c in sorted(coeffs.items(), key=lambda kv: index[kv[0]])]
+        a = f"a{namp}"
+        namp += 1
+        k = len(seq)
+        if k == 1:
+            A, B = seq[0]
+            if "JTT" not in prog.values:
+                prog.dens[mtt] = "gluon"
+                define("JTT", [Op("ffv_v0", "JTT", ["wT", "wTB"], {"m": mtt})])
+            ops = [Op("amp_vvv", a, ["JTT", tree(A), tree(B)], {"mX": mtt, "mA": gmask(A), "mB": gmask(B)})]
+            if not isinstance(B, int):
+                ops.append(Op("amp_vvvv_acc", a, [a, "JTT", tree(A), tree(B[0]), tree(B[1])], {"sgn": 1}))
+            if not isinstance(A, int):
+                ops.append(Op("amp_vvvv_acc", a, [a, "JTT", tree(B), tree(A[0]), tree(A[1])], {"sgn": -1}))
+        else:
+            j = min(range(1, k + 1), key=lambda jj: (new_currents(seq, jj), abs(2 * jj - (k + 1))))
+            ops = [Op("amp_ffv", a, [row(seq[:j - 1]), tree(seq[j - 1]), col(seq[j:])], {})]
+        ops.append(Op("jamp", None, [a], {"jam": jam}))
+        deps = []
+        for op in ops:
+            for v in op.ins:
+                if v != a and v not in deps:
+                    deps.append(v)
+        prog.items.append((ops, deps))
+    return prog
+
+
+# --------------------------------------------------------------- ee -> mumu
+def eemumu_program() -> Program:
+    """e+ e- > mu+ mu- through s-channel photon and Z (2 diagrams)."""
+    prog = Program(name="eemumu", process="e+ e- > mu+ mu-", npar=4, leg_sign=[1, 1, -1, -1],
+                   ncolor=1, colour_num=[[1]], colour_den=1, iden=4, n_diagrams=2)
+    V = prog.values
+    V["w0"] = [Op("ext_vbar", "w0", [], {"leg": 0})]    # incoming e+
+    V["w1"] = [Op("ext_u", "w1", [], {"leg": 1})]       # incoming e-
+    V["w2"] = [Op("ext_v", "w2", [], {"leg": 2})]       # outgoing mu+
+    V["w3"] = [Op("ext_ubar", "w3", [], {"leg": 3})]    # outgoing mu-
+    m = 0b0011
+    V["JA"] = [Op("ffv_v0_ew", "JA", ["w0", "w1"], {"m": m})]
+    V["JZ"] = [Op("ffv_vm_ew", "JZ", ["w0", "w1"], {"m": m})]
+    for k in ("w0", "w1", "w2", "w3"):
+        prog.deps[k] = []
+    prog.deps["JA"] = prog.deps["JZ"] = ["w0", "w1"]
+    prog.dens[m] = "z"
+    ops = [Op("amp_ffv_ew", "a0", ["w3", "JA", "w2"], {}),
+           Op("amp_ffv_ew_acc", "a0", ["a0", "w3", "JZ", "w2"], {}),
+           Op("jamp", None, ["a0"], {"jam": [(0, 1 + 0j)]})]
+    prog.items.append((ops, ["w3", "JA", "w2", "JZ"]))
+    return prog
+
+
+# --------------------------------------------------------------- scheduling
+def _closure(prog, names):
+    seen = []
+    stack = list(names)
+    while stack:
+        v = stack.pop()
+        if v in seen:
+            continue
+        seen.append(v)
+        stack.extend(prog.deps.get(v, []))
+    return seen
+
+
+def schedule(prog: Program, budget: int) -> Program:
+    """Linearise the DAG for one lane with at most ``budget`` live
+    wavefunctions (recomputing evicted ones).  Amplitudes are taken greedily:
+    next is the one whose missing wavefunctions are cheapest to compute given
+    the current cache.  Recomputed copies get a new name '<v>_r<k>' and are
+    marked so the code generator can keep the compiler from merging them
+    with the first copy."""
+    items = list(prog.items)
+    closures = [set(_closure(prog, deps)) for _, deps in items]
+    vcost = {v: max(1, prog.flops_of(ops)) for v, ops in prog.values.items()}
+    remaining = set(range(len(items)))
+    # next-use is evaluated against the items still to come, in their
+    # original order, as a proxy for the greedy order chosen on the fly
+    uses = {}
+    for i in range(len(items)):
+        for v in closures[i]:
+            uses.setdefault(v, []).append(i)
+
+    def next_use(v):
+        best = len(items) + 1
+        for i in uses.get(v, []):
+            if i in remaining:
+                # distance in "remaining" order: the number of remaining items before it
+                best = i
+                break
+        return best
+
+    cache = {}          # value -> current emitted name
+    version = {}
+    out = []
+
+    def rename(op, names):
+        ins = [names.get(v, cache.get(v, v)) for v in op.ins]
+        return Op(op.kind, names.get(op.out, op.out) if op.out else None, ins, dict(op.prm))
+
+    def evict(pinned):
+        while len(cache) > budget:
+            cands = [v for v in cache if v not in pinned]
+            if not cands:
+                return
+            victim = max(cands, key=next_use)
+            del cache[victim]
+
+    def ensure(v, pinned):
+        if v in cache:
+            return cache[v]
+        pinned = pinned | {v}
+        for d in prog.deps.get(v, []):
+            ensure(d, pinned)
+            pinned = pinned | {d}
+        k = version.get(v, 0)
+        version[v] = k + 1
+        nm = v if k == 0 else f"{v}_r{k}"
+        names = {v: nm}
+        for op in prog.values[v]:
+            o = rename(op, names)
+            if k > 0:
+                o.prm["recompute"] = True
+            out.append(o)
+        cache[v] = nm
+        evict(pinned | set(prog.deps.get(v, [])))
+        return nm
+
+    def missing_cost(i):
+        return sum(vcost[v] for v in closures[i] if v not in cache)
+
+    order = []
+    while remaining:
+        i = min(remaining, key=lambda j: (missing_cost(j), j))
+        remaining.discard(i)
+        order.append(i)
+        ops, deps = items[i]
+        pinned = set()
+        for d in deps:
+            ensure(d, pinned)
+            pinned.add(d)
+        for op in ops:
+            out.append(rename(op, {}))
+        evict(set())
+    prog.items = [items[i] for i in order]
+    prog.ops = out
+    return prog
+
+
+def peak_live(prog: Program) -> int:
+    """Peak number of simultaneously live wavefunctions in prog.ops."""
+    last = {}
+    for i, op in enumerate(prog.ops):
+        for v in op.ins:
+            last[v] = i
+    live, peak = set(), 0
+    for i, op in enumerate(prog.ops):
+        if op.out and op.kind not in ("amp_ffv", "amp_vvv", "amp_vvvv_acc", "amp_ffv_ew", "amp_ffv_ew_acc"):
+            live.add(op.out)
+        peak = max(peak, len(live))
+        for v in op.ins:
+            if last.get(v) == i:
+                live.discard(v)
+    return peak
+
+
+def all_programs(budget=None):
+    progs = [eemumu_program()] + [qcd_program(ng) for ng in (2, 3, 4, 5)]
+    for p in progs:
+        schedule(p, budget if budget is not None else DEFAULT_BUDGET.get(p.name, 24))
+    return progs
+
+
+DEFAULT_BUDGET = {"eemumu": 8, "ggtt": 8, "ggttg": 12, "ggttgg": 14, "ggttggg": 16}

@@ -1,0 +1,153 @@
+"""GPU path vs the CPU oracle, element by element, through the C ABI.
+
+FP64 form: relative error <= 1e-12 per event (the tolerance the build
+targets for the FP64 path).  Mixed form: median relative error <= 1e-5 and
+maximum <= 1e-3.  Sizes: the oracle checks every event of batches that span
+many 256-event blocks plus a ragged tail, and a random sample of events of
+the full-size configurations the benchmark runs.
+"""
+import numpy as np
+import pytest
+
+from paper_2312_02898_amd.inputs import CONFIGS, config_events
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+PROCS = ["eemumu", "ggtt", "ggttg", "ggttgg"]
+# events checked element-wise against the oracle (all of ee->mumu's batch)
+NCHECK = {"eemumu": 16384, "ggtt": 4096 + 37, "ggttg": 2048 + 37, "ggttgg": 1024 + 37}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2312_02898_amd import binding
+    binding.lib()
+    return binding
+
+
+def _me(B, proc, precision, **kw):
+    from paper_2312_02898_amd.engine import MatrixElement
+    return MatrixElement(proc, precision=precision, **kw)
+
+
+def _run(me, mom_np, dev):
+    m = torch.from_numpy(mom_np).to(dev)
+    out = me(m)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def _rel(a, b):
+    return np.abs(a / b - 1.0)
+
+
+@pytest.mark.parametrize("proc", PROCS)
+def test_fp64_matches_oracle(oracle_lib, B, dev, proc):
+    mom = config_events(proc, NCHECK[proc])
+    name = CONFIGS[proc][0]
+    print(f"[fp64 parity] {proc} nevt={mom.shape[0]}", flush=True)
+    me = _me(B, proc, "fp64")
+    gpu = _run(me, mom, dev)
+    ref = oracle_lib.me(name, mom)
+    rel = _rel(gpu, ref)
+    print(f"  max rel {rel.max():.3e} median {np.median(rel):.3e}", flush=True)
+    assert np.isfinite(gpu).all() and (gpu > 0).all()
+    assert rel.max() <= 1e-12
+
+
+@pytest.mark.parametrize("proc", PROCS)
+def test_fp64_full_size_sampled(oracle_lib, B, dev, proc):
+    """Full benchmark batch in the launch configuration the benchmark uses;
+    the oracle checks a random sample of its events."""
+    mom = config_events(proc)
+    name = CONFIGS[proc][0]
+    print(f"[fp64 full] {proc} nevt={mom.shape[0]}", flush=True)
+    me = _me(B, proc, "fp64")
+    gpu = _run(me, mom, dev)
+    assert np.isfinite(gpu).all() and (gpu > 0).all()
+    rng = np.random.default_rng(123)
+    idx = np.sort(rng.choice(mom.shape[0], size=128, replace=False))
+    ref = oracle_lib.me(name, mom[idx])
+    assert _rel(gpu[idx], ref).max() <= 1e-12
+
+
+@pytest.mark.parametrize("proc", PROCS)
+def test_mixed_precision_error(oracle_lib, B, dev, proc):
+    mom = config_events(proc, NCHECK[proc])
+    name = CONFIGS[proc][0]
+    print(f"[mixed parity] {proc} nevt={mom.shape[0]}", flush=True)
+    me = _me(B, proc, "mixed")
+    gpu = _run(me, mom, dev)
+    ref = oracle_lib.me(name, mom)
+    rel = _rel(gpu, ref)
+    print(f"  mixed median {np.median(rel):.3e} p99 {np.quantile(rel, 0.99):.3e} max {rel.max():.3e}", flush=True)
+    assert np.median(rel) <= 1e-5
+    assert rel.max() <= 1e-3
+
+
+@pytest.mark.parametrize("proc", PROCS)
+def test_per_helicity_and_filter(oracle_lib, B, dev, proc):
+    """|M_h|^2 of every helicity matches the oracle; the filter keeps every
+    helicity that is alive on the configuration's events."""
+    mom = config_events(proc, 64)
+    name = CONFIGS[proc][0]
+    me = _me(B, proc, "fp64")
+    m = torch.from_numpy(mom).to(dev)
+    gh = me.helicities(m)
+    torch.cuda.synchronize()
+    gh = gh.cpu().numpy()
+    oh = oracle_lib.me_hel(name, mom)
+    scale = oh.sum(axis=1, keepdims=True)
+    assert (np.abs(gh - oh) / scale).max() <= 1e-12
+    live = np.nonzero((oh / scale).max(axis=0) > 1e-20)[0]
+    good = set(me.good_helicities())
+    assert set(live.tolist()) <= good
+    # the filtered sum equals the unfiltered one
+    me_all = _me(B, proc, "fp64", filter_helicities=False)
+    a = _run(me, mom, dev)
+    b = _run(me_all, mom, dev)
+    assert _rel(a, b).max() <= 1e-13
+
+
+@pytest.mark.parametrize("proc", ["ggtt", "ggttgg"])
+def test_ragged_sizes_and_determinism(B, dev, proc):
+    """nevt in {1, 63, 64, 65, 255, 257}: each result equals the same events
+    inside a larger batch bit for bit, and reruns are bitwise identical."""
+    mom = config_events(proc, 1000)
+    me = _me(B, proc, "fp64")
+    full = _run(me, mom, dev)
+    again = _run(me, mom, dev)
+    assert np.array_equal(full, again)
+    for n in (1, 63, 64, 65, 255, 257):
+        part = _run(me, np.ascontiguousarray(mom[:n]), dev)
+        assert np.array_equal(part, full[:n])
+    off = _run(me, np.ascontiguousarray(mom[311:311 + 77]), dev)
+    assert np.array_equal(off, full[311:311 + 77])
+
+
+def test_abi_errors(B, dev):
+    import ctypes
+    with pytest.raises(B.MeError) as e:
+        B.me_create("g g > t t~ t t~")
+    assert e.value.status == B.ME_EPROCESS
+    h = B.me_create("g g > t t~")
+    # nevt == 0 is a no-op, null pointers and negative sizes are rejected
+    assert B.lib().me_compute(h, None, 0, None, None) == B.ME_OK
+    assert B.lib().me_compute(h, None, 5, None, None) == B.ME_EINVAL
+    assert B.lib().me_compute(h, ctypes.c_void_p(16), -1, ctypes.c_void_p(16), None) == B.ME_EINVAL
+    assert B.lib().me_compute(None, ctypes.c_void_p(16), 1, ctypes.c_void_p(16), None) == B.ME_EINVAL
+    info = B.me_info(h)
+    assert info["npar"] == 4 and info["ndiagrams"] == 3 and info["ncolor"] == 2 and info["nhel"] == 16
+    B.me_helicity_filter(h)
+    B.me_helicity_filter(h)   # idempotent
+    assert B.me_info(h)["nhel_good"] == 12
+    B.me_destroy(h)
