@@ -309,6 +309,10 @@ template <class T> __device__ __forceinline__ wf<T> opaque(wf<T> w) {
   for (int m = 0; m < 4; ++m) asm volatile("" : "+v"(w.c[m].r), "+v"(w.c[m].i));
   return w;
 }
+__device__ __forceinline__ double opaque_d(double x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
 template <class T> __device__ __forceinline__ void acc_scaled(wf<T>& o, const wf<T>& v, T s) {
   for (int m = 0; m < 4; ++m) o.c[m] = o.c[m] + s * v.c[m];
 }

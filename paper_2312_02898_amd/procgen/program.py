@@ -86,20 +86,23 @@ class Program:
         for op in ops:
             if op.kind == "jamp":
                 f += 2 * len(op.prm["jam"])
+            elif op.kind == "kmom":
+                f += 4 * (bin(op.prm["mk"]).count("1") - 1)
+            elif op.kind == "den":
+                f += 4 * (bin(op.prm["mk"]).count("1") - 1) + DEN_FLOPS[op.prm["kind"]]
             else:
                 f += FLOPS.get(op.kind, 0)
         return f
 
     def flops_per_helicity(self) -> int:
-        """Algorithmic flops of one helicity: every distinct vertex call once
-        (no recomputation), propagator factors, jamp updates, colour form."""
+        """Algorithmic flops of one helicity: every distinct vertex call,
+        momentum sum and propagator factor once (no recomputation), jamp
+        updates, colour quadratic form."""
         f = 0
         for ops in self.values.values():
             f += self.flops_of(ops)
         for ops, _ in self.items:
             f += self.flops_of(ops)
-        for m, kind in self.dens.items():
-            f += 4 * (bin(m).count("1") - 1) + DEN_FLOPS[kind]
         n = self.ncolor
         f += 2 * n * (n + 1) + 4 * n
         return f
@@ -107,8 +110,6 @@ class Program:
     def executed_flops_per_helicity(self) -> int:
         """Flops of the scheduled code including recomputation."""
         f = self.flops_of(self.ops)
-        for m, kind in self.dens.items():
-            f += 4 * (bin(m).count("1") - 1) + DEN_FLOPS[kind]
         n = self.ncolor
         return f + 2 * n * (n + 1) + 4 * n
 
@@ -121,6 +122,59 @@ class Program:
 
 def _incoming_count(mask):
     return (mask & 1) + ((mask >> 1) & 1)
+
+
+# register footprint of a value in FP64 dwords (the FP32 form needs about half)
+def value_size(name: str) -> int:
+    if name.startswith("K"):      # momentum sum (4 reals)
+        return 8
+    if name.startswith("D"):      # complex propagator factor
+        return 4
+    if name.startswith("I"):      # real propagator factor 1/K^2
+        return 2
+    return 16                     # complex 4-component wavefunction
+
+
+def add_kinematics(prog: "Program", op: "Op") -> "Op":
+    """Make the momentum sums (K<mask>) and propagator factors (D<mask> for
+    massive, I<mask> for massless lines) an op needs explicit inputs, so the
+    scheduler bounds their live ranges like any other value."""
+    extra = []
+    for key in ("mA", "mB", "mX"):
+        if key in op.prm:
+            extra.append(kmom(prog, op.prm[key]))
+    m = op.prm.get("m")
+    if m is not None:
+        kind = prog.dens[m]
+        if op.kind in ("ffv_fin", "ffv_fout", "ffv_vm_ew"):
+            extra.append(kmom(prog, m))
+        if kind in ("top_t", "top_s"):
+            extra.append(den(prog, m, "D"))
+        elif kind == "z":
+            extra.append(den(prog, m, "D"))
+            extra.append(den(prog, m, "I"))
+        else:
+            extra.append(den(prog, m, "I"))
+    for v in extra:
+        if v not in op.ins:
+            op.ins.append(v)
+    return op
+
+
+def kmom(prog, m):
+    name = f"K{m}"
+    if name not in prog.values:
+        prog.values[name] = [Op("kmom", name, [], {"mk": m})]
+        prog.deps[name] = []
+    return name
+
+
+def den(prog, m, tag):
+    name = f"{tag}{m}"
+    if name not in prog.values:
+        prog.values[name] = [Op("den", name, [], {"mk": m, "kind": prog.dens[m], "tag": tag})]
+        prog.deps[name] = []
+    return name
 
 
 # ------------------------------------------------------------------ QCD
@@ -195,6 +249,7 @@ def qcd_program(ng: int) -> Program:
                    colour_den=cden, iden=iden, n_diagrams=feynman_diagram_count(ng))
 
     def define(name, ops):
+        ops = [add_kinematics(prog, op) for op in ops]
         prog.values[name] = ops
         deps = []
         for op in ops:
@@ -296,6 +351,7 @@ def qcd_program(ng: int) -> Program:
         else:
             j = min(range(1, k + 1), key=lambda jj: (new_currents(seq, jj), abs(2 * jj - (k + 1))))
             ops = [Op("amp_ffv", a, [row(seq[:j - 1]), tree(seq[j - 1]), col(seq[j:])], {})]
+        ops = [add_kinematics(prog, op) for op in ops]
         ops.append(Op("jamp", None, [a], {"jam": jam}))
         deps = []
         for op in ops:
@@ -311,18 +367,20 @@ def eemumu_program() -> Program:
     """e+ e- > mu+ mu- through s-channel photon and Z (2 diagrams)."""
     prog = Program(name="eemumu", process="e+ e- > mu+ mu-", npar=4, leg_sign=[1, 1, -1, -1],
                    ncolor=1, colour_num=[[1]], colour_den=1, iden=4, n_diagrams=2)
-    V = prog.values
-    V["w0"] = [Op("ext_vbar", "w0", [], {"leg": 0})]    # incoming e+
-    V["w1"] = [Op("ext_u", "w1", [], {"leg": 1})]       # incoming e-
-    V["w2"] = [Op("ext_v", "w2", [], {"leg": 2})]       # outgoing mu+
-    V["w3"] = [Op("ext_ubar", "w3", [], {"leg": 3})]    # outgoing mu-
     m = 0b0011
-    V["JA"] = [Op("ffv_v0_ew", "JA", ["w0", "w1"], {"m": m})]
-    V["JZ"] = [Op("ffv_vm_ew", "JZ", ["w0", "w1"], {"m": m})]
-    for k in ("w0", "w1", "w2", "w3"):
-        prog.deps[k] = []
-    prog.deps["JA"] = prog.deps["JZ"] = ["w0", "w1"]
     prog.dens[m] = "z"
+
+    def define(name, ops):
+        ops = [add_kinematics(prog, op) for op in ops]
+        prog.values[name] = ops
+        prog.deps[name] = [v for op in ops for v in op.ins if v != name]
+
+    define("w0", [Op("ext_vbar", "w0", [], {"leg": 0})])    # incoming e+
+    define("w1", [Op("ext_u", "w1", [], {"leg": 1})])       # incoming e-
+    define("w2", [Op("ext_v", "w2", [], {"leg": 2})])       # outgoing mu+
+    define("w3", [Op("ext_ubar", "w3", [], {"leg": 3})])    # outgoing mu-
+    define("JA", [Op("ffv_v0_ew", "JA", ["w0", "w1"], {"m": m})])
+    define("JZ", [Op("ffv_vm_ew", "JZ", ["w0", "w1"], {"m": m})])
     ops = [Op("amp_ffv_ew", "a0", ["w3", "JA", "w2"], {}),
            Op("amp_ffv_ew_acc", "a0", ["a0", "w3", "JZ", "w2"], {}),
            Op("jamp", None, ["a0"], {"jam": [(0, 1 + 0j)]})]
@@ -344,8 +402,9 @@ def _closure(prog, names):
 
 
 def schedule(prog: Program, budget: int) -> Program:
-    """Linearise the DAG for one lane with at most ``budget`` live
-    wavefunctions (recomputing evicted ones).  Amplitudes are taken greedily:
+    """Linearise the DAG for one lane with at most ``budget`` live register
+    dwords of cached values (FP64 sizes; recomputing evicted ones).
+    Amplitudes are taken greedily:
     next is the one whose missing wavefunctions are cheapest to compute given
     the current cache.  Recomputed copies get a new name '<v>_r<k>' and are
     marked so the code generator can keep the compiler from merging them
@@ -379,11 +438,12 @@ def schedule(prog: Program, budget: int) -> Program:
         return Op(op.kind, names.get(op.out, op.out) if op.out else None, ins, dict(op.prm))
 
     def evict(pinned):
-        while len(cache) > budget:
+        while sum(value_size(v) for v in cache) > budget:
             cands = [v for v in cache if v not in pinned]
             if not cands:
                 return
-            victim = max(cands, key=next_use)
+            # furthest next use, weighted by footprint over recompute cost
+            victim = max(cands, key=lambda v: (next_use(v) - cur[0] + 1) * value_size(v) / vcost[v])
             del cache[victim]
 
     def ensure(v, pinned):
@@ -410,8 +470,10 @@ def schedule(prog: Program, budget: int) -> Program:
         return sum(vcost[v] for v in closures[i] if v not in cache)
 
     order = []
+    cur = [0]
     while remaining:
         i = min(remaining, key=lambda j: (missing_cost(j), j))
+        cur[0] = i
         remaining.discard(i)
         order.append(i)
         ops, deps = items[i]
@@ -428,16 +490,16 @@ def schedule(prog: Program, budget: int) -> Program:
 
 
 def peak_live(prog: Program) -> int:
-    """Peak number of simultaneously live wavefunctions in prog.ops."""
+    """Peak FP64 dwords of simultaneously live cached values in prog.ops."""
     last = {}
     for i, op in enumerate(prog.ops):
         for v in op.ins:
             last[v] = i
     live, peak = set(), 0
     for i, op in enumerate(prog.ops):
-        if op.out and op.kind not in ("amp_ffv", "amp_vvv", "amp_vvvv_acc", "amp_ffv_ew", "amp_ffv_ew_acc"):
+        if op.out and not op.out.startswith("a"):
             live.add(op.out)
-        peak = max(peak, len(live))
+        peak = max(peak, sum(value_size(v.split("_r")[0]) for v in live))
         for v in op.ins:
             if last.get(v) == i:
                 live.discard(v)
@@ -447,8 +509,8 @@ def peak_live(prog: Program) -> int:
 def all_programs(budget=None):
     progs = [eemumu_program()] + [qcd_program(ng) for ng in (2, 3, 4, 5)]
     for p in progs:
-        schedule(p, budget if budget is not None else DEFAULT_BUDGET.get(p.name, 24))
+        schedule(p, budget if budget is not None else DEFAULT_BUDGET.get(p.name, 256))
     return progs
 
 
-DEFAULT_BUDGET = {"eemumu": 8, "ggtt": 8, "ggttg": 12, "ggttgg": 14, "ggttggg": 16}
+DEFAULT_BUDGET = {"eemumu": 256, "ggtt": 256, "ggttg": 320, "ggttgg": 320, "ggttggg": 320}

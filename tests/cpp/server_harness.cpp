@@ -1,0 +1,115 @@
+// CPU driver of the serving core with a fake executor: each request
+// "runs" for a synthetic service time, results are written by the host, and
+// failures can be injected at launch or at finish.  Prints one JSON object.
+#include <atomic>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "server_core.hpp"
+
+using clk = std::chrono::steady_clock;
+
+struct FakeExec {
+  double service_s = 0.01;
+  int fail_launch_ticket = -1, fail_finish_ticket = -1;
+  std::vector<clk::time_point> t0;
+  std::vector<int64_t> slot_ticket;
+  std::mutex mu;
+  std::vector<int64_t> admit_order;
+  std::vector<std::pair<double, double>> intervals;   // (start, end) per finished request
+  clk::time_point origin = clk::now();
+  std::atomic<int> concurrent{0}, max_concurrent{0};
+
+  explicit FakeExec(int nslots) : t0(nslots), slot_ticket(nslots, -1) {}
+  bool launch(int slot, me::Request& r, int64_t) {
+    std::lock_guard<std::mutex> lk(mu);
+    admit_order.push_back(r.ticket);
+    if (r.ticket == fail_launch_ticket) return false;
+    t0[slot] = clk::now();
+    slot_ticket[slot] = r.ticket;
+    int c = ++concurrent;
+    if (c > max_concurrent) max_concurrent = c;
+    return true;
+  }
+  bool done(int slot) {
+    return std::chrono::duration<double>(clk::now() - t0[slot]).count() >= service_s;
+  }
+  bool finish(int slot, me::Request& r, int64_t) {
+    std::lock_guard<std::mutex> lk(mu);
+    --concurrent;
+    intervals.push_back({std::chrono::duration<double>(t0[slot] - origin).count(),
+                         std::chrono::duration<double>(clk::now() - origin).count()});
+    for (int64_t i = 0; i < r.nevt; ++i) r.h_out[i] = r.h_mom[i * 4 * r.npar] * 2.0;
+    return r.ticket != fail_finish_ticket;
+  }
+};
+
+int main(int argc, char** argv) {
+  std::string sc = argc > 1 ? argv[1] : "basic";
+  int nslots = sc == "memory" ? 8 : 4;
+  int64_t budget = sc == "memory" ? 300000 : (1 << 20);   // "memory": about 2 requests fit
+  int nreq = sc == "overlap" ? 8 : 12;
+  int64_t nevt = 1000;   // 1000 * (32*4 + 8) = 136000 B, ~7 fit in 1 MiB
+  FakeExec ex(nslots);
+  if (sc == "fail") { ex.fail_launch_ticket = 3; ex.fail_finish_ticket = 7; }
+  if (sc == "overlap") ex.service_s = 0.05;
+  std::vector<std::vector<double>> in(nreq), out(nreq);
+  int64_t rejected_rc = 0;
+  std::vector<int64_t> tickets;
+  {
+    me::ServerCore<FakeExec> core(ex, budget, nslots);
+    auto tstart = clk::now();
+    for (int i = 0; i < nreq; ++i) {
+      int64_t n = nevt + 37 * i;
+      in[i].assign(n * 16, 0.0);
+      for (int64_t e = 0; e < n; ++e) in[i][e * 16] = double(i * 100000 + e);
+      out[i].assign(n, -1.0);
+      me::Request r;
+      r.h_mom = in[i].data(); r.h_out = out[i].data(); r.nevt = n; r.npar = 4;
+      int64_t t = -1;
+      int rc = core.submit(r, &t);
+      tickets.push_back(rc == 0 ? t : -1);
+    }
+    // oversize request and invalid request
+    std::vector<double> big(16 * 100000), bigo(100000);
+    me::Request rb; rb.h_mom = big.data(); rb.h_out = bigo.data(); rb.nevt = 100000; rb.npar = 4;
+    int64_t tb;
+    rejected_rc = core.submit(rb, &tb);
+    me::Request bad; bad.h_mom = big.data(); bad.h_out = bigo.data(); bad.nevt = 0; bad.npar = 4;
+    int bad_rc = core.submit(bad, &tb);
+    std::vector<int> status(nreq);
+    std::vector<double> lat(nreq);
+    for (int i = 0; i < nreq; ++i) {
+      me::TicketState st; bool known;
+      bool ok = core.wait(tickets[i], 30.0, &st, &known);
+      status[i] = ok ? st.status : 999;
+      lat[i] = st.latency_s;
+    }
+    double wall = std::chrono::duration<double>(clk::now() - tstart).count();
+    me::ServerStats s = core.stats();
+    int correct = 1;
+    for (int i = 0; i < nreq; ++i)
+      if (status[i] == 0)
+        for (size_t e = 0; e < out[i].size(); ++e)
+          if (out[i][e] != 2.0 * in[i][e * 16]) correct = 0;
+    printf("{\"scenario\": \"%s\", \"wall\": %.6f, \"rejected_rc\": %lld, \"bad_rc\": %d, \"correct\": %d,"
+           " \"submitted\": %lld, \"completed\": %lld, \"failed\": %lld, \"rejected\": %lld,"
+           " \"bytes_in_use\": %lld, \"peak_bytes\": %lld, \"budget\": %lld, \"max_concurrent\": %d,"
+           " \"status\": [", sc.c_str(), wall, (long long)rejected_rc, bad_rc, correct,
+           (long long)s.submitted, (long long)s.completed, (long long)s.failed, (long long)s.rejected,
+           (long long)s.bytes_in_use, (long long)s.peak_bytes_in_use, (long long)budget, ex.max_concurrent.load());
+    for (int i = 0; i < nreq; ++i) printf("%s%d", i ? ", " : "", status[i]);
+    printf("], \"latency\": [");
+    for (int i = 0; i < nreq; ++i) printf("%s%.6f", i ? ", " : "", lat[i]);
+    printf("], \"admit_order\": [");
+    for (size_t i = 0; i < ex.admit_order.size(); ++i) printf("%s%lld", i ? ", " : "", (long long)ex.admit_order[i]);
+    printf("], \"tickets\": [");
+    for (int i = 0; i < nreq; ++i) printf("%s%lld", i ? ", " : "", (long long)tickets[i]);
+    printf("]}\n");
+  }
+  return 0;
+}

@@ -1,0 +1,118 @@
+"""Host logic of the process compiler: diagram enumeration, colour algebra,
+and validity of the scheduled straight-line programs."""
+import itertools
+import re
+
+import numpy as np
+import pytest
+
+from paper_2312_02898_amd.procgen import colour, program
+
+
+@pytest.mark.parametrize("ng,count", [(2, 3), (3, 16), (4, 123), (5, 1240)])
+def test_feynman_diagram_counts(ng, count):
+    """3 / 16 / 123 / 1240 tree diagrams for gg -> ttbar + 0..3 g."""
+    assert program.feynman_diagram_count(ng) == count
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+def test_colour_matrix_fierz_equals_bruteforce(oracle_lib, n):
+    """Fierz algebra (build time) and explicit Gell-Mann sums (oracle) agree."""
+    num, den = colour.colour_matrix(n)
+    C = np.array(num, dtype=float) / den
+    assert np.abs(C - oracle_lib.colour_matrix(n)).max() < 1e-10 * np.abs(C).max()
+
+
+def test_tree_expansion_commutator_and_jacobi():
+    e = colour.expand((0, 1))
+    assert e == {(0, 1): -1j, (1, 0): 1j}
+    # Jacobi: f^{x a e} f^{e b c} + cyclic = 0
+    tot = {}
+    for t in [(0, (1, 2)), (1, (2, 0)), (2, (0, 1))]:
+        for k, v in colour.expand(t).items():
+            tot[k] = tot.get(k, 0) + v
+    assert all(abs(v) == 0 for v in tot.values())
+
+
+def test_colour_expansion_matches_explicit_matrices(oracle_lib):
+    """E(T1..Tk) contracted with explicit colours equals the direct product of
+    t's and f's for a few trees (f from the oracle's structure constants is
+    not used: f^{abc} t^c = -i[t^a, t^b] is applied numerically)."""
+    rng = np.random.default_rng(1)
+    for seq in [((0, 1), 2), (0, (1, 2)), ((0, (1, 2)),), (((0, 1), 2),)]:
+        exp = colour.expand_line(seq)
+        n = 3
+        for _ in range(5):
+            col = list(rng.choice([0, 1, 2, 3, 4, 7], size=n)) + list(rng.integers(0, 3, size=2))
+            basis = oracle_lib.colour_basis(n, col)
+            order = colour.basis(n)
+            val = sum(c * basis[order.index(s)] for s, c in exp.items())
+            # direct: replace every tree node by -i[t^L, t^R] with explicit matrices
+            T = _gellmann()
+
+            def mat(t):
+                if isinstance(t, (int, np.integer)):
+                    return T[col[t]]
+                A, B = mat(t[0]), mat(t[1])
+                return -1j * (A @ B - B @ A)
+            M = np.eye(3, dtype=complex)
+            for t in seq:
+                M = M @ mat(t)
+            assert abs(val - M[col[n], col[n + 1]]) < 1e-13
+
+
+def _gellmann():
+    l = np.zeros((8, 3, 3), complex)
+    l[0][0, 1] = l[0][1, 0] = 1
+    l[1][0, 1], l[1][1, 0] = -1j, 1j
+    l[2][0, 0], l[2][1, 1] = 1, -1
+    l[3][0, 2] = l[3][2, 0] = 1
+    l[4][0, 2], l[4][2, 0] = -1j, 1j
+    l[5][1, 2] = l[5][2, 1] = 1
+    l[6][1, 2], l[6][2, 1] = -1j, 1j
+    l[7] = np.diag([1, 1, -2]) / np.sqrt(3)
+    return l / 2
+
+
+@pytest.mark.parametrize("ng,items", [(2, 3), (3, 15), (4, 105), (5, 945)])
+def test_program_items(ng, items):
+    """One amplitude per (sequence of binary trees) on the top line; the
+    four-gluon pieces are folded into the trees."""
+    p = program.qcd_program(ng)
+    assert len(p.items) == items
+
+
+@pytest.mark.parametrize("budget", [128, 256, 320, 512])
+@pytest.mark.parametrize("ng", [3, 4])
+def test_schedule_is_valid(ng, budget):
+    """Every value is defined before use, every amplitude is accumulated
+    exactly once, and recomputation only re-derives values the DAG defines."""
+    p = program.qcd_program(ng)
+    program.schedule(p, budget)
+    defined = set()
+    jamps = 0
+    for op in p.ops:
+        for v in op.ins:
+            if op.kind in ("vvvv_acc", "amp_vvvv_acc", "amp_ffv_ew_acc") and v == op.out:
+                continue
+            assert v in defined, (op.kind, v)
+        if op.out:
+            base = re.sub(r"_r\d+$", "", op.out)
+            assert base in p.values or base.startswith("a")
+            defined.add(op.out)
+        if op.kind == "jamp":
+            jamps += 1
+    assert jamps == len(p.items)
+    # the inputs one vertex call needs at once may briefly exceed a tiny budget
+    assert program.peak_live(p) <= budget + 96
+
+
+def test_every_colour_string_reached():
+    """The jamps of ggttgg receive contributions for all 24 orderings."""
+    p = program.qcd_program(4)
+    seen = set()
+    for ops, _ in p.items:
+        for op in ops:
+            if op.kind == "jamp":
+                seen |= {i for i, _ in op.prm["jam"]}
+    assert seen == set(range(24))
