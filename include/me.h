@@ -65,9 +65,14 @@ enum {
 };
 
 typedef enum {
-  ME_FP64 = 0,  /* all arithmetic in FP64 */
-  ME_MIXED = 1  /* FP32 wavefunctions and vertices; FP64 momenta, p^2,
-                   propagator denominators and helicity-sum accumulation */
+  ME_FP64 = 0,       /* all arithmetic in FP64 */
+  ME_MIXED = 1,      /* FP32 wavefunctions and vertices; FP64 momenta, p^2,
+                        propagator denominators and helicity-sum accumulation;
+                        colour sum on MFMA (FP16 hi+lo jamps, exact FP16
+                        colour matrix, FP32 accumulation) for 6..32 colour
+                        flows, FP32 vector ALU otherwise */
+  ME_MIXED_VALU = 2  /* as ME_MIXED with the colour sum always on the FP32
+                        vector ALU */
 } me_precision;
 
 /* Standard-Model inputs.  me_default_params() fills the benchmark values

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "colour_mfma.hpp"
 #include "helas.hpp"
 #include "me_types.h"
 
@@ -58,7 +59,43 @@ __global__ __launch_bounds__(256) void me_kernel(const double* __restrict__ mom,
   if (out) out[e] = acc * (1.0 / (P::CDEN * P::IDEN));
 }
 
-// mode: ME_MODE_FP64 or ME_MODE_MIXED.  out_hel (FP64 only) receives the
+// Mixed form with the colour sum on MFMA.  Every lane of a wave stays active
+// through the helicity loop (the MFMA needs the whole wave); lanes past the
+// end of the batch evaluate the last event again and do not store.
+template <class P>
+__global__ __launch_bounds__(256) void me_kernel_mfma(const double* __restrict__ mom, int64_t nevt,
+                                                      double* __restrict__ out, const MeParams prm) {
+  __shared__ __attribute__((aligned(16))) _Float16 lds_all[4 * (kColourLdsBytes / 2)];
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int64_t e0 = int64_t(blockIdx.x) * blockDim.x + 64 * wave;
+  if (e0 >= nevt) return;   // whole wave past the end (wave-uniform)
+  const int64_t e = e0 + lane;
+  const int64_t ec = e < nevt ? e : nevt - 1;
+  _Float16* lds = lds_all + wave * (kColourLdsBytes / 2);
+  const ColourB<P::NCOLOR> B = colour_b<P::NCOLOR>(P::cmat(), lane);
+  double p[P::NPAR][4];
+  const double2* src = reinterpret_cast<const double2*>(mom + ec * (4 * P::NPAR));
+#pragma unroll
+  for (int i = 0; i < P::NPAR; ++i) {
+    const double2 a = src[2 * i], b = src[2 * i + 1];
+    p[i][0] = a.x; p[i][1] = a.y; p[i][2] = b.x; p[i][3] = b.y;
+  }
+  double acc = 0.0;
+  for (int ih = 0; ih < prm.nhel; ++ih) {
+#pragma unroll
+    for (int i = 0; i < P::NPAR; ++i)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) asm volatile("" : "+v"(p[i][c]));
+    const unsigned hel = prm.hel[ih];
+    cx<float> jamp[P::NCOLOR];
+    P::template amplitudes<float>(p, hel, prm, jamp);
+    acc += double(colour_sum_mfma<P::NCOLOR>(jamp, B, lds, lane));
+  }
+  if (e < nevt) out[e] = acc * (1.0 / (P::CDEN * P::IDEN));
+}
+
+// mode: ME_MODE_FP64, ME_MODE_MIXED (MFMA colour sum where it pays, i.e. for
+// 6 to 32 colour flows) or ME_MODE_MIXED_VALU (colour sum on the vector ALU).  out_hel (FP64 only) receives the
 // colour-summed |M_h|^2 of every listed helicity, [nevt][NHEL].
 template <class P>
 int launch(int mode, const double* mom, int64_t nevt, double* out, double* out_hel, const MeParams& prm,
@@ -70,7 +107,10 @@ int launch(int mode, const double* mom, int64_t nevt, double* out, double* out_h
   if (mode == ME_MODE_FP64) {
     hipLaunchKernelGGL((me_kernel<P, double>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
                        out_hel, prm);
-  } else if (mode == ME_MODE_MIXED) {
+  } else if (mode == ME_MODE_MIXED && P::NCOLOR >= 6 && P::NCOLOR <= 32) {
+    if (out_hel || !out) return -1;
+    hipLaunchKernelGGL((me_kernel_mfma<P>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out, prm);
+  } else if (mode == ME_MODE_MIXED || mode == ME_MODE_MIXED_VALU) {
     if (out_hel) return -1;
     hipLaunchKernelGGL((me_kernel<P, float>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
                        nullptr, prm);

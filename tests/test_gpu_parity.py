@@ -80,12 +80,13 @@ def test_fp64_full_size_sampled(oracle_lib, B, dev, proc):
     assert _rel(gpu[idx], ref).max() <= 1e-12
 
 
+@pytest.mark.parametrize("precision", ["mixed", "mixed_valu"])
 @pytest.mark.parametrize("proc", PROCS)
-def test_mixed_precision_error(oracle_lib, B, dev, proc):
+def test_mixed_precision_error(oracle_lib, B, dev, proc, precision):
     mom = config_events(proc, NCHECK[proc])
     name = CONFIGS[proc][0]
-    print(f"[mixed parity] {proc} nevt={mom.shape[0]}", flush=True)
-    me = _me(B, proc, "mixed")
+    print(f"[{precision} parity] {proc} nevt={mom.shape[0]}", flush=True)
+    me = _me(B, proc, precision)
     gpu = _run(me, mom, dev)
     ref = oracle_lib.me(name, mom)
     rel = _rel(gpu, ref)
@@ -151,3 +152,16 @@ def test_abi_errors(B, dev):
     B.me_helicity_filter(h)   # idempotent
     assert B.me_info(h)["nhel_good"] == 12
     B.me_destroy(h)
+
+
+@pytest.mark.parametrize("proc", ["ggttg", "ggttgg"])
+def test_mfma_colour_sum_matches_valu(B, dev, proc):
+    """The MFMA colour sum (FP16 hi+lo jamps, FP32 accumulation) agrees with
+    the FP32 vector-ALU colour sum of the same FP32 jamps, including a batch
+    with a ragged last wave."""
+    mom = config_events(proc, 2048 + 29)
+    a = _run(_me(B, proc, "mixed"), mom, dev)
+    b = _run(_me(B, proc, "mixed_valu"), mom, dev)
+    rel = _rel(a, b)
+    print(f"  mfma vs valu median {np.median(rel):.3e} max {rel.max():.3e}", flush=True)
+    assert np.median(rel) < 1e-6 and rel.max() < 1e-5
