@@ -65,7 +65,7 @@ def build(processes=None, jobs=None, verbose=True) -> str:
     srcs = codegen.generate(GEN, names=procs)
     hdrs = [os.path.join(CSRC, f) for f in ("helas.hpp", "kernels.hpp", "me_types.h")]
     table = os.path.join(GEN, "process_table.inc")
-    units = [(s, hdrs) for s in srcs]
+    units = [(s, hdrs + [s.replace(".hip", "_proc.inc")]) for s in srcs]
     units.append((os.path.join(CSRC, "runtime.cpp"), hdrs + [table, os.path.join(ROOT, "include", "me.h")]))
     server = os.path.join(CSRC, "server.cpp")
     if os.path.exists(server):

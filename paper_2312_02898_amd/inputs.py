@@ -15,8 +15,9 @@ the paper is silent:
     frame: p1 = (sqrt(s)/2)(1,0,0,1), p2 = (sqrt(s)/2)(1,0,0,-1);
   * massive final states: the massless momenta are rescaled by xi solving
     sum_i sqrt(m_i^2 + xi^2 p0_i^2) = sqrt(s) with Newton's method from
-    xi0 = sqrt(1 - (sum m / sqrt s)^2), stopping at |residual| <= 1e-14 sqrt(s)
-    or after 50 steps.
+    xi0 = sqrt(1 - (sum m / sqrt s)^2), stopping at |residual| <= 4 eps sqrt(s)
+    (extended precision) or after 50 steps;
+  * all arithmetic in extended precision, one rounding to double at the end.
 """
 from __future__ import annotations
 
@@ -33,52 +34,84 @@ PROCESS_LEGS = {
 
 
 def rambo(nevt: int, sqrt_s: float, final_masses, seed: int, rng=None) -> np.ndarray:
-    """Return float64 momenta [nevt][2 + nfinal][4] as (E, px, py, pz)."""
+    """Return float64 momenta [nevt][2 + nfinal][4] as (E, px, py, pz).
+
+    The arithmetic runs in x87 extended precision (numpy longdouble) and is
+    rounded to double once at the end, and the invariant mass of the massless
+    seeds is formed as sum_{i<j} q0_i q0_j |n_i - n_j|^2 (no cancellation), so
+    the events are on shell and balanced to a few ulps of double even for
+    nearly collinear seeds.  Plain double RAMBO leaves ~1e-11 relative
+    off-shell noise on such events, which different spinor constructions
+    turn into different |M|^2 at that level."""
+    L = np.longdouble
     masses = np.asarray(final_masses, dtype=np.float64)
     n = masses.size
     if rng is None:
         rng = np.random.Generator(np.random.PCG64(seed))
-    r = rng.random((nevt, n, 4))
-    c = 2.0 * r[..., 0] - 1.0
-    phi = 2.0 * np.pi * r[..., 1]
-    q0 = -np.log((1.0 - r[..., 2]) * (1.0 - r[..., 3]))
-    st = np.sqrt(np.maximum(0.0, 1.0 - c * c))
-    q = np.empty((nevt, n, 4))
+    r = rng.random((nevt, n, 4)).astype(L)
+    one, two = L(1), L(2)
+    c = two * r[..., 0] - one
+    phi = two * np.arccos(L(-1)) * r[..., 1]
+    q0 = -np.log((one - r[..., 2]) * (one - r[..., 3]))
+    st = np.sqrt(np.maximum(L(0), one - c * c))
+    nhat = np.empty((nevt, n, 3), dtype=L)
+    nhat[..., 0] = st * np.cos(phi)
+    nhat[..., 1] = st * np.sin(phi)
+    nhat[..., 2] = c
+    q = np.empty((nevt, n, 4), dtype=L)
     q[..., 0] = q0
-    q[..., 1] = q0 * st * np.cos(phi)
-    q[..., 2] = q0 * st * np.sin(phi)
-    q[..., 3] = q0 * c
+    q[..., 1:] = q0[..., None] * nhat
     Q = q.sum(axis=1)
-    M = np.sqrt(Q[:, 0] ** 2 - Q[:, 1] ** 2 - Q[:, 2] ** 2 - Q[:, 3] ** 2)
+    M2 = np.zeros(nevt, dtype=L)
+    for i in range(n):
+        for j in range(i + 1, n):
+            d = nhat[:, i] - nhat[:, j]
+            M2 += q0[:, i] * q0[:, j] * (d * d).sum(axis=-1)
+    M = np.sqrt(M2)
     b = -Q[:, 1:] / M[:, None]
     gamma = Q[:, 0] / M
-    a = 1.0 / (1.0 + gamma)
-    x = sqrt_s / M
-    bq = np.einsum("ek,enk->en", b, q[..., 1:])
+    a = one / (one + gamma)
+    x = L(sqrt_s) / M
+    bq = (b[:, None, :] * q[..., 1:]).sum(axis=-1)
     p = np.empty_like(q)
     p[..., 0] = x[:, None] * (gamma[:, None] * q[..., 0] + bq)
     p[..., 1:] = x[:, None, None] * (q[..., 1:] + b[:, None, :] * q[..., 0:1]
                                      + a[:, None, None] * bq[..., None] * b[:, None, :])
-    if np.any(masses > 0):
-        p = _rescale_massive(p, masses, sqrt_s)
+    if n == 2:
+        # two bodies: the event is fixed by one direction; rebuild the
+        # back-to-back pair from RAMBO's direction so it is exactly on shell
+        # and balanced (the conformal boost loses ~gamma^2 eps of accuracy for
+        # nearly collinear seeds)
+        nd = p[:, 0, 1:] / np.sqrt((p[:, 0, 1:] ** 2).sum(axis=-1))[:, None]
+        sq = L(sqrt_s)
+        m1, m2 = L(masses[0]), L(masses[1])
+        e1 = (sq * sq + m1 * m1 - m2 * m2) / (two * sq)
+        e2 = sq - e1
+        pabs = np.sqrt(np.maximum(L(0), e1 * e1 - m1 * m1))
+        p[:, 0, 0], p[:, 1, 0] = e1, e2
+        p[:, 0, 1:] = pabs * nd
+        p[:, 1, 1:] = -pabs * nd
+    elif np.any(masses > 0):
+        p = _rescale_massive(p, masses.astype(L), L(sqrt_s))
     out = np.empty((nevt, n + 2, 4))
     e = 0.5 * sqrt_s
     out[:, 0] = (e, 0.0, 0.0, e)
     out[:, 1] = (e, 0.0, 0.0, -e)
-    out[:, 2:] = p
+    out[:, 2:] = p.astype(np.float64)
     return out
 
 
-def _rescale_massive(p: np.ndarray, masses: np.ndarray, sqrt_s: float) -> np.ndarray:
+def _rescale_massive(p, masses, sqrt_s):
     if masses.sum() >= sqrt_s:
         raise ValueError("sqrt(s) below the production threshold")
     m2 = masses[None, :] ** 2
     p02 = p[..., 0] ** 2
-    xi = np.full(p.shape[0], np.sqrt(1.0 - (masses.sum() / sqrt_s) ** 2))
+    xi = np.full(p.shape[0], np.sqrt(1 - (masses.sum() / sqrt_s) ** 2))
+    tol = 4 * np.finfo(np.longdouble).eps * sqrt_s
     for _ in range(50):
         e = np.sqrt(m2 + (xi[:, None] ** 2) * p02)
         f = e.sum(axis=1) - sqrt_s
-        todo = np.abs(f) > 1e-14 * sqrt_s      # per event, so a batch's prefix is reproducible
+        todo = np.abs(f) > tol      # per event, so a batch's prefix is reproducible
         if not np.any(todo):
             break
         df = (xi[:, None] * p02 / e).sum(axis=1)
