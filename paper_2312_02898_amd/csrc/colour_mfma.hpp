@@ -2,17 +2,20 @@
 //
 // For each helicity the wave holds jamp[NCOLOR] (FP32 complex) per lane.
 // q_e = x_e^T C x_e + y_e^T C y_e (x = Re jamp, y = Im jamp, C the integer
-// colour matrix) is evaluated as the dense product  D = X C  on
-// v_mfma_f32_16x16x32_f16 (M = 64 events in 4 tiles, N = K = colours padded to
-// 32) followed by the row-wise dot q_e = sum_k X[e][k] D[e][k]:
+// colour matrix) is evaluated as the dense product  D' = C X^T  on
+// v_mfma_f32_16x16x32_f16 (M = colours, N = 64 events in 4 tiles, K =
+// colours, padded to 32), followed by each lane's dot of its own row of D
+// with its own jamps:
 //   * per (event, helicity) a power-of-two scale 2^-s brings max|jamp| below 1
 //     (exact), then X = hi + lo with hi = f16(x), lo = f16(x - hi): about 22
 //     significant bits;
 //   * C has at most 10 significant bits (integers <= 512 for 4 gluons), so it
-//     is exact in FP16 and hi*C, lo*C are exact in the FP32 accumulator;
-//   * X goes through LDS to reach the MFMA operand layout (row = event,
-//     8 consecutive colours per lane); C is loaded once per kernel into the B
-//     operand registers.
+//     is exact in FP16 and C*hi, C*lo are exact in the FP32 accumulator;
+//   * C is the A operand, loaded once per kernel into registers; X reaches
+//     the B operand layout through LDS (8 consecutive colours of one event per
+//     lane, one 128-bit load); a lane's D' fragment is 4 consecutive colours
+//     of one event, stored with one 128-bit write; each lane then reads its own
+//     row back.
 // MFMA operand layout (16x16x32, wave64): lane l supplies A[l%16][8(l/16)+j]
 // and B[8(l/16)+j][l%16] for j = 0..7, and receives D[4(l/16)+i][l%16] for
 // i = 0..3.  Only the pairing of A's and B's K slots matters for the product,
@@ -37,26 +40,27 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Per-wave LDS: 4 planes (Re hi, Re lo, Im hi, Im lo) of [64 events][32 colours]
-// halves plus 64 floats for the results = 16640 bytes.
-constexpr int kColourLdsHalves = 4 * 64 * 32;
-constexpr int kColourLdsBytes = kColourLdsHalves * 2 + 64 * 4;
+// Per-wave LDS: hi and lo planes [64 events][32 colours] of halves (8 KB) and
+// the product rows [64 events][32 colours] of floats (8 KB), reused for the
+// real and the imaginary part.
+constexpr int kColourLdsBytes = 2 * 64 * 32 * 2 + 64 * 32 * 4;
 
 template <int NC>
-struct ColourB {
-  half8 b[2];   // B operand for N-tiles 0 and 1
+struct ColourA {
+  half8 a[2];   // A operand (colour matrix) for colour tiles 0 and 1
 };
 
-// B operand registers from the integer colour matrix (row-major NC x NC).
+// A operand registers from the integer colour matrix (row-major NC x NC):
+// lane l holds C[16m + l%16][8(l/16) + j].
 template <int NC>
-__device__ __forceinline__ ColourB<NC> colour_b(const int* cmat, int lane) {
-  ColourB<NC> r;
+__device__ __forceinline__ ColourA<NC> colour_a(const int* cmat, int lane) {
+  ColourA<NC> r;
 #pragma unroll
-  for (int n = 0; n < 2; ++n) {
+  for (int m = 0; m < 2; ++m) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const int k = 8 * (lane / 16) + j, col = 16 * n + lane % 16;
-      r.b[n][j] = (k < NC && col < NC) ? _Float16(float(cmat[k * NC + col])) : _Float16(0.0f);
+      const int row = 16 * m + lane % 16, k = 8 * (lane / 16) + j;
+      r.a[m][j] = (row < NC && k < NC) ? _Float16(float(cmat[row * NC + k])) : _Float16(0.0f);
     }
   }
   return r;
@@ -65,66 +69,63 @@ __device__ __forceinline__ ColourB<NC> colour_b(const int* cmat, int lane) {
 // Returns sum_kl C_kl Re(conj(jamp_k) jamp_l) for this lane's event; every
 // lane of the wave must call it (uniform control flow).
 template <int NC>
-__device__ __forceinline__ float colour_sum_mfma(const cx<float> (&jamp)[NC], const ColourB<NC>& B,
-                                                 _Float16* lds, int lane) {
+__device__ __forceinline__ float colour_sum_mfma(const cx<float> (&jamp)[NC], const ColourA<NC>& A,
+                                                 void* lds_wave, int lane) {
   static_assert(NC <= 32, "MFMA colour sum handles up to 32 colour flows");
-  float* qbuf = reinterpret_cast<float*>(lds + kColourLdsHalves);
-  // power-of-two scale: max |component| -> [0.5, 1)
+  _Float16* phi = reinterpret_cast<_Float16*>(lds_wave);
+  _Float16* plo = phi + 64 * 32;
+  float* drow = reinterpret_cast<float*>(plo + 64 * 32);
   float m = 0.f;
 #pragma unroll
   for (int k = 0; k < NC; ++k) m = fmaxf(m, fmaxf(fabsf(jamp[k].r), fabsf(jamp[k].i)));
   int ex = 0;
   (void)frexpf(m, &ex);
-  // write hi/lo planes, rows = events, 32 colours (zero padded)
-#pragma unroll
-  for (int k = 0; k < 32; ++k) {
-    float xr = 0.f, xi = 0.f;
-    if (k < NC) { xr = ldexpf(jamp[k].r, -ex); xi = ldexpf(jamp[k].i, -ex); }
-    const _Float16 hr = _Float16(xr), hi = _Float16(xi);
-    lds[(0 * 64 + lane) * 32 + k] = hr;
-    lds[(1 * 64 + lane) * 32 + k] = _Float16(xr - float(hr));
-    lds[(2 * 64 + lane) * 32 + k] = hi;
-    lds[(3 * 64 + lane) * 32 + k] = _Float16(xi - float(hi));
-  }
-  wave_lds_sync();
   const int g = lane / 16, c16 = lane % 16;
+  float q = 0.f;
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    float part[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int ri = 0; ri < 2; ++ri) {
+    // this lane's event row: scaled hi/lo halves, 8 colours per 128-bit store
 #pragma unroll
-    for (int ri = 0; ri < 2; ++ri) {           // real, imaginary
-      const half8 ahi = *reinterpret_cast<const half8*>(&lds[((2 * ri) * 64 + 16 * t + c16) * 32 + 8 * g]);
-      const half8 alo = *reinterpret_cast<const half8*>(&lds[((2 * ri + 1) * 64 + 16 * t + c16) * 32 + 8 * g]);
+    for (int c = 0; c < 4; ++c) {
+      half8 h, l;
 #pragma unroll
-      for (int n = 0; n < 2; ++n) {
-        if (16 * n >= NC) continue;
+      for (int j = 0; j < 8; ++j) {
+        const int k = 8 * c + j;
+        const float x = k < NC ? ldexpf(ri ? jamp[k < NC ? k : 0].i : jamp[k < NC ? k : 0].r, -ex) : 0.f;
+        const _Float16 hx = _Float16(x);
+        h[j] = hx;
+        l[j] = _Float16(x - float(hx));
+      }
+      *reinterpret_cast<half8*>(&phi[lane * 32 + 8 * c]) = h;
+      *reinterpret_cast<half8*>(&plo[lane * 32 + 8 * c]) = l;
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const half8 bhi = *reinterpret_cast<const half8*>(&phi[(16 * t + c16) * 32 + 8 * g]);
+      const half8 blo = *reinterpret_cast<const half8*>(&plo[(16 * t + c16) * 32 + 8 * g]);
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        if (16 * mt >= NC) continue;
         float4v d = {0.f, 0.f, 0.f, 0.f};
-        d = mfma16x16x32(ahi, B.b[n], d);
-        d = mfma16x16x32(alo, B.b[n], d);
-        // this lane holds D[e][k] for e = 16t + 4g + i, k = 16n + c16
-        const int k = 16 * n + c16;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int e = 16 * t + 4 * g + i;
-          const float x = float(lds[((2 * ri) * 64 + e) * 32 + k]) + float(lds[((2 * ri + 1) * 64 + e) * 32 + k]);
-          part[i] += x * d[i];
-        }
+        d = mfma16x16x32(A.a[mt], bhi, d);
+        d = mfma16x16x32(A.a[mt], blo, d);
+        // d[i] = (C X^T)[16mt + 4g + i][16t + c16]
+        *reinterpret_cast<float4v*>(&drow[(16 * t + c16) * 32 + 16 * mt + 4 * g]) = d;
       }
     }
-    // sum over the 16 lanes of the group (colour index)
+    wave_lds_sync();
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      float v = part[i];
-      v += __shfl_xor(v, 8, 16);
-      v += __shfl_xor(v, 4, 16);
-      v += __shfl_xor(v, 2, 16);
-      v += __shfl_xor(v, 1, 16);
-      if (c16 == i) qbuf[16 * t + 4 * g + i] = v;
+    for (int c = 0; c < (NC + 3) / 4; ++c) {
+      const float4v d = *reinterpret_cast<const float4v*>(&drow[lane * 32 + 4 * c]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = 4 * c + i;
+        if (k < NC) q += ldexpf(ri ? jamp[k].i : jamp[k].r, -ex) * d[i];
+      }
     }
+    wave_lds_sync();   // the next pass overwrites the planes and rows
   }
-  wave_lds_sync();
-  const float q = qbuf[lane];
-  wave_lds_sync();   // the next call overwrites the planes
   return ldexpf(q, 2 * ex);
 }
 

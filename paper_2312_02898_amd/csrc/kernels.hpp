@@ -53,10 +53,10 @@ __global__ __launch_bounds__(256) void me_kernel(const double* __restrict__ mom,
     cx<T> jamp[P::NCOLOR];
     P::template amplitudes<T>(p, hel, prm, jamp);
     const double q = double(P::template colour_sum<T>(jamp));
-    if (out_hel) out_hel[e * P::NHEL + hel] = q * (1.0 / P::CDEN);
+    if (out_hel) out_hel[e * P::NHEL + hel] = q * (P::coupling_factor(prm) / P::CDEN);
     acc += q;
   }
-  if (out) out[e] = acc * (1.0 / (P::CDEN * P::IDEN));
+  if (out) out[e] = acc * (P::coupling_factor(prm) / (P::CDEN * P::IDEN));
 }
 
 // Mixed form with the colour sum on MFMA.  Every lane of a wave stays active
@@ -65,14 +65,14 @@ __global__ __launch_bounds__(256) void me_kernel(const double* __restrict__ mom,
 template <class P>
 __global__ __launch_bounds__(256) void me_kernel_mfma(const double* __restrict__ mom, int64_t nevt,
                                                       double* __restrict__ out, const MeParams prm) {
-  __shared__ __attribute__((aligned(16))) _Float16 lds_all[4 * (kColourLdsBytes / 2)];
+  __shared__ __attribute__((aligned(16))) char lds_all[4 * kColourLdsBytes];
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int64_t e0 = int64_t(blockIdx.x) * blockDim.x + 64 * wave;
   if (e0 >= nevt) return;   // whole wave past the end (wave-uniform)
   const int64_t e = e0 + lane;
   const int64_t ec = e < nevt ? e : nevt - 1;
-  _Float16* lds = lds_all + wave * (kColourLdsBytes / 2);
-  const ColourB<P::NCOLOR> B = colour_b<P::NCOLOR>(P::cmat(), lane);
+  void* lds = lds_all + wave * kColourLdsBytes;
+  const ColourA<P::NCOLOR> A = colour_a<P::NCOLOR>(P::cmat(), lane);
   double p[P::NPAR][4];
   const double2* src = reinterpret_cast<const double2*>(mom + ec * (4 * P::NPAR));
 #pragma unroll
@@ -89,9 +89,9 @@ __global__ __launch_bounds__(256) void me_kernel_mfma(const double* __restrict__
     const unsigned hel = prm.hel[ih];
     cx<float> jamp[P::NCOLOR];
     P::template amplitudes<float>(p, hel, prm, jamp);
-    acc += double(colour_sum_mfma<P::NCOLOR>(jamp, B, lds, lane));
+    acc += double(colour_sum_mfma<P::NCOLOR>(jamp, A, lds, lane));
   }
-  if (e < nevt) out[e] = acc * (1.0 / (P::CDEN * P::IDEN));
+  if (e < nevt) out[e] = acc * (P::coupling_factor(prm) / (P::CDEN * P::IDEN));
 }
 
 // mode: ME_MODE_FP64, ME_MODE_MIXED (MFMA colour sum where it pays, i.e. for

@@ -76,7 +76,9 @@ class Program:
     deps: dict = field(default_factory=dict)     # name -> list of value names
     items: list = field(default_factory=list)    # (list[Op] amplitude ops + jamp op, deps)
     dens: dict = field(default_factory=dict)     # mask -> propagator kind
-    ops: list = field(default_factory=list)      # scheduled straight-line code
+    ops: list = field(default_factory=list)      # scheduled straight-line code (last schedule)
+    ops_f64: list = field(default_factory=list)  # schedule for the FP64 form
+    ops_f32: list = field(default_factory=list)  # schedule for the FP32 form
 
     def value_masks(self, op: Op):
         return [v for k, v in op.prm.items() if k.startswith("m")]
@@ -484,7 +486,9 @@ def schedule(prog: Program, budget: int) -> Program:
         for op in ops:
             out.append(rename(op, {}))
         evict(set())
-    prog.items = [items[i] for i in order]
+    # prog.items keeps the builder's order so that every schedule starts from
+    # the same point; the chosen order is kept separately
+    prog.order = order
     prog.ops = out
     return prog
 
@@ -507,10 +511,19 @@ def peak_live(prog: Program) -> int:
 
 
 def all_programs(budget=None):
+    """Programs with one register schedule per arithmetic type.  Budgets are
+    in FP64 dwords; an FP32 value takes half the registers, so the FP32
+    schedule gets the same register count as twice the FP64 budget."""
     progs = [eemumu_program()] + [qcd_program(ng) for ng in (2, 3, 4, 5)]
     for p in progs:
-        schedule(p, budget if budget is not None else DEFAULT_BUDGET.get(p.name, 256))
+        b64 = budget if budget is not None else DEFAULT_BUDGET_F64.get(p.name, 256)
+        b32 = budget if budget is not None else DEFAULT_BUDGET_F32.get(p.name, 512)
+        schedule(p, b32)
+        p.ops_f32 = p.ops
+        schedule(p, b64)
+        p.ops_f64 = p.ops
     return progs
 
 
-DEFAULT_BUDGET = {"eemumu": 256, "ggtt": 256, "ggttg": 320, "ggttgg": 320, "ggttggg": 320}
+DEFAULT_BUDGET_F64 = {"eemumu": 256, "ggtt": 256, "ggttg": 320, "ggttgg": 320, "ggttggg": 320}
+DEFAULT_BUDGET_F32 = {"eemumu": 256, "ggtt": 256, "ggttg": 384, "ggttgg": 384, "ggttggg": 384}
