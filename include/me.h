@@ -71,8 +71,11 @@ typedef enum {
                         colour sum on MFMA (FP16 hi+lo jamps, exact FP16
                         colour matrix, FP32 accumulation) for 6..32 colour
                         flows, FP32 vector ALU otherwise */
-  ME_MIXED_VALU = 2  /* as ME_MIXED with the colour sum always on the FP32
+  ME_MIXED_VALU = 2, /* as ME_MIXED with the colour sum always on the FP32
                         vector ALU */
+  ME_MIXED_MFMA32 = 3 /* as ME_MIXED with the colour sum on MFMA with FP32
+                        operands (exact FP32 jamps and colour matrix, no
+                        hi+lo split) for 6..32 colour flows */
 } me_precision;
 
 /* Standard-Model inputs.  me_default_params() fills the benchmark values
@@ -142,6 +145,16 @@ me_status me_destroy(me_handle h);
 
 /* Thread-local text of the last error (never NULL). */
 const char* me_last_error(void);
+
+/* GPU-assisted batch unweighting (paper, Sec. 3 and Table 2): event weights
+ * w_i = d_me[i] * d_factor[i] (|M|^2 times the Jacobian x PDF factor) formed
+ * on the device, and their maximum over the batch written to *d_max (device
+ * memory, one double).  Negative or NaN products count as 0.  d_w [nevt]
+ * receives the weights if non-NULL.  All pointers are device pointers;
+ * asynchronous on hip_stream; nevt == 0 gives *d_max = 0.  The caller owns
+ * every buffer; nothing is allocated. */
+me_status me_max_weight(const double* d_me, const double* d_factor, int64_t nevt, double* d_w,
+                        double* d_max, void* hip_stream);
 
 /* ------------------------------------------------------------ serving --
  * A persistent request loop for uneven |M|^2 batches of several processes,

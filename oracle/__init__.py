@@ -177,3 +177,11 @@ def colour_matrix(ngluons):
     if lib().oracle_colour_matrix(int(ngluons), _dp(out)) != 0:
         raise ValueError("oracle_colour_matrix failed")
     return out
+
+
+def max_weight(me_values, factors):
+    """Batch unweighting step (paper, Sec. 3): weights w_i = |M|^2_i f_i
+    (negative or NaN products count as 0) and their maximum."""
+    w = np.asarray(me_values, dtype=np.float64) * np.asarray(factors, dtype=np.float64)
+    w = np.where(w > 0, w, 0.0)
+    return w, (float(w.max()) if w.size else 0.0)

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libme_mi355x.so")
 
 ME_OK, ME_EINVAL, ME_EPROCESS, ME_ENOMEM, ME_EHIP, ME_ENOTSUP, ME_EBUSY = 0, -1, -2, -3, -4, -5, -6
-ME_FP64, ME_MIXED, ME_MIXED_VALU = 0, 1, 2
+ME_FP64, ME_MIXED, ME_MIXED_VALU, ME_MIXED_MFMA32 = 0, 1, 2, 3
 
 
 class MeError(RuntimeError):
@@ -78,7 +78,7 @@ EXPORTS = [
     "me_default_params", "me_create", "me_helicity_filter", "me_compute", "me_compute_helicities",
     "me_good_helicities", "me_info", "me_destroy", "me_last_error",
     "me_server_create", "me_server_submit", "me_server_poll", "me_server_wait", "me_server_stats",
-    "me_server_destroy",
+    "me_server_destroy", "me_max_weight",
 ]
 
 _lib = None
@@ -105,6 +105,7 @@ def lib():
         for name in EXPORTS:
             if name not in ("me_default_params", "me_last_error") and hasattr(L, name):
                 getattr(L, name).restype = i32
+        L.me_max_weight.argtypes = [vp, vp, i64, vp, vp, vp]
         if hasattr(L, "me_server_create"):
             L.me_server_create.argtypes = [i64, i32, P(vp)]
             L.me_server_submit.argtypes = [vp, vp, vp, i64, vp, P(i64)]
@@ -164,6 +165,12 @@ def me_info(handle: int) -> dict:
 
 def me_destroy(handle: int) -> None:
     _check(lib().me_destroy(handle), "me_destroy")
+
+
+def me_max_weight(d_me: int, d_factor: int, nevt: int, d_w: int, d_max: int, stream: int = 0) -> None:
+    """Device pointers in; *d_max receives max_i(me_i * factor_i)."""
+    _check(lib().me_max_weight(d_me or None, d_factor or None, nevt, d_w or None, d_max or None, stream or None),
+           "me_max_weight")
 
 
 def me_last_error() -> str:

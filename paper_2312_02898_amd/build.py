@@ -67,9 +67,9 @@ def build(processes=None, jobs=None, verbose=True) -> str:
     table = os.path.join(GEN, "process_table.inc")
     units = [(s, hdrs + [s.replace(".hip", "_proc.inc")]) for s in srcs]
     units.append((os.path.join(CSRC, "runtime.cpp"), hdrs + [table, os.path.join(ROOT, "include", "me.h")]))
-    server = os.path.join(CSRC, "server.cpp")
-    if os.path.exists(server):
-        units.append((server, hdrs + [os.path.join(ROOT, "include", "me.h")]))
+    for extra in ("server.cpp", "unweight.cpp"):
+        units.append((os.path.join(CSRC, extra),
+                      hdrs + [os.path.join(CSRC, "server_core.hpp"), os.path.join(ROOT, "include", "me.h")]))
     jobs = jobs or min(len(units), os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda u: _compile(*u), units))

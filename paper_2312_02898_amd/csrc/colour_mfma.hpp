@@ -129,4 +129,92 @@ __device__ __forceinline__ float colour_sum_mfma(const cx<float> (&jamp)[NC], co
   return ldexpf(q, 2 * ex);
 }
 
+// ---------------------------------------------------------------------------
+// The same contraction with FP32 operands on v_mfma_f32_16x16x4_f32: jamps
+// and the integer colour matrix are exact FP32 operands, so there is no
+// scaling and no hi/lo split, and the result has the rounding of an FP32
+// accumulation only.  K runs over colours in steps of 4; in step s lane group
+// g supplies colour kappa = S*g + s (S = ceil(NC/4) steps), so each lane
+// reads S consecutive colours of one event from LDS.
+// Operand layout (16x16x4, wave64): lane l supplies A[l%16][l/16] and
+// B[l/16][l%16], and receives D[4(l/16)+i][l%16].
+
+__device__ __forceinline__ float4v mfma16x16x4f32(float a, float b, float4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <int NC>
+struct ColourA32 {
+  static constexpr int S = (NC + 3) / 4;
+  float a[2][S];   // A operand (colour matrix) for colour tiles 0 and 1, K steps
+};
+
+template <int NC>
+__device__ __forceinline__ ColourA32<NC> colour_a32(const int* cmat, int lane) {
+  ColourA32<NC> r;
+  constexpr int S = ColourA32<NC>::S;
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int st = 0; st < S; ++st) {
+      const int row = 16 * m + lane % 16, k = S * (lane / 16) + st;
+      r.a[m][st] = (row < NC && k < NC) ? float(cmat[row * NC + k]) : 0.f;
+    }
+  return r;
+}
+
+// Per-wave LDS: x rows [64][32] floats (8 KB) and product rows [64][32] (8 KB).
+constexpr int kColourLds32Bytes = 2 * 64 * 32 * 4;
+
+template <int NC>
+__device__ __forceinline__ float colour_sum_mfma32(const cx<float> (&jamp)[NC], const ColourA32<NC>& A,
+                                                   void* lds_wave, int lane) {
+  static_assert(NC <= 32, "MFMA colour sum handles up to 32 colour flows");
+  constexpr int S = ColourA32<NC>::S;
+  float* xrow = reinterpret_cast<float*>(lds_wave);
+  float* drow = xrow + 64 * 32;
+  const int g = lane / 16, c16 = lane % 16;
+  float q = 0.f;
+#pragma unroll
+  for (int ri = 0; ri < 2; ++ri) {
+#pragma unroll
+    for (int c = 0; c < (NC + 3) / 4; ++c) {
+      float4v v;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = 4 * c + i;
+        v[i] = k < NC ? (ri ? jamp[k < NC ? k : 0].i : jamp[k < NC ? k : 0].r) : 0.f;
+      }
+      *reinterpret_cast<float4v*>(&xrow[lane * 32 + 4 * c]) = v;
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      float b[S];
+#pragma unroll
+      for (int st = 0; st < S; ++st) b[st] = xrow[(16 * t + c16) * 32 + S * g + st];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        if (16 * mt >= NC) continue;
+        float4v d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int st = 0; st < S; ++st) d = mfma16x16x4f32(A.a[mt][st], b[st], d);
+        *reinterpret_cast<float4v*>(&drow[(16 * t + c16) * 32 + 16 * mt + 4 * g]) = d;
+      }
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int c = 0; c < (NC + 3) / 4; ++c) {
+      const float4v d = *reinterpret_cast<const float4v*>(&drow[lane * 32 + 4 * c]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = 4 * c + i;
+        if (k < NC) q += (ri ? jamp[k].i : jamp[k].r) * d[i];
+      }
+    }
+    wave_lds_sync();
+  }
+  return q;
+}
+
 }  // namespace me

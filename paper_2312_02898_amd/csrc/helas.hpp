@@ -173,6 +173,38 @@ __device__ __forceinline__ cx<T> ffv_amp(const wf<T>& r, const wf<T>& J, const w
   return mul_i(gR * x + gL * y);
 }
 
+// Half contractions, for amplitudes that share a row spinor and a vector
+// (or a vector and a column spinor):
+//   row  s = rbar gamma.J (gL P_L + gR P_R),   column  x = gamma.J (gL P_L + gR P_R) psi,
+// and the amplitude  i (row . column).
+template <class T>
+__device__ __forceinline__ wf<T> ffv_half_row(const wf<T>& r, const wf<T>& J, T gL, T gR) {
+  const jsig<T> q = sig(J);
+  wf<T> o;
+  o.c[0] = gL * (r.c[2] * q.a + r.c[3] * q.c);
+  o.c[1] = gL * (r.c[2] * q.d + r.c[3] * q.b);
+  o.c[2] = gR * (r.c[0] * q.b - r.c[1] * q.c);
+  o.c[3] = gR * (r.c[1] * q.a - r.c[0] * q.d);
+  return o;
+}
+template <class T>
+__device__ __forceinline__ wf<T> ffv_half_col(const wf<T>& J, const wf<T>& s, T gL, T gR) {
+  const jsig<T> q = sig(J);
+  wf<T> o;
+  o.c[0] = gR * (q.b * s.c[2] - q.d * s.c[3]);
+  o.c[1] = gR * (q.a * s.c[3] - q.c * s.c[2]);
+  o.c[2] = gL * (q.a * s.c[0] + q.d * s.c[1]);
+  o.c[3] = gL * (q.c * s.c[0] + q.b * s.c[1]);
+  return o;
+}
+template <class T> __device__ __forceinline__ cx<T> amp_dot(const wf<T>& r, const wf<T>& c) {
+  cx<T> t = r.c[0] * c.c[0];
+  t = cfma(r.c[1], c.c[1], t);
+  t = cfma(r.c[2], c.c[2], t);
+  t = cfma(r.c[3], c.c[3], t);
+  return mul_i(t);
+}
+
 // Off-shell column spinor  i(K/+m)/(K^2-m^2+i m G) [i gamma.J (gL P_L+gR P_R)] psi.
 // K: momentum along the arrow (into the next vertex); den = 1/(K^2-m^2+i m G).
 template <class T>

@@ -62,17 +62,19 @@ __global__ __launch_bounds__(256) void me_kernel(const double* __restrict__ mom,
 // Mixed form with the colour sum on MFMA.  Every lane of a wave stays active
 // through the helicity loop (the MFMA needs the whole wave); lanes past the
 // end of the batch evaluate the last event again and do not store.
-template <class P>
+template <class P, bool F32OPS>
 __global__ __launch_bounds__(256) void me_kernel_mfma(const double* __restrict__ mom, int64_t nevt,
                                                       double* __restrict__ out, const MeParams prm) {
-  __shared__ __attribute__((aligned(16))) char lds_all[4 * kColourLdsBytes];
+  constexpr int kLds = F32OPS ? kColourLds32Bytes : kColourLdsBytes;
+  __shared__ __attribute__((aligned(16))) char lds_all[4 * kLds];
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int64_t e0 = int64_t(blockIdx.x) * blockDim.x + 64 * wave;
   if (e0 >= nevt) return;   // whole wave past the end (wave-uniform)
   const int64_t e = e0 + lane;
   const int64_t ec = e < nevt ? e : nevt - 1;
-  void* lds = lds_all + wave * kColourLdsBytes;
+  void* lds = lds_all + wave * kLds;
   const ColourA<P::NCOLOR> A = colour_a<P::NCOLOR>(P::cmat(), lane);
+  const ColourA32<P::NCOLOR> A32 = colour_a32<P::NCOLOR>(P::cmat(), lane);
   double p[P::NPAR][4];
   const double2* src = reinterpret_cast<const double2*>(mom + ec * (4 * P::NPAR));
 #pragma unroll
@@ -89,7 +91,10 @@ __global__ __launch_bounds__(256) void me_kernel_mfma(const double* __restrict__
     const unsigned hel = prm.hel[ih];
     cx<float> jamp[P::NCOLOR];
     P::template amplitudes<float>(p, hel, prm, jamp);
-    acc += double(colour_sum_mfma<P::NCOLOR>(jamp, A, lds, lane));
+    if constexpr (F32OPS)
+      acc += double(colour_sum_mfma32<P::NCOLOR>(jamp, A32, lds, lane));
+    else
+      acc += double(colour_sum_mfma<P::NCOLOR>(jamp, A, lds, lane));
   }
   if (e < nevt) out[e] = acc * (P::coupling_factor(prm) / (P::CDEN * P::IDEN));
 }
@@ -107,10 +112,15 @@ int launch(int mode, const double* mom, int64_t nevt, double* out, double* out_h
   if (mode == ME_MODE_FP64) {
     hipLaunchKernelGGL((me_kernel<P, double>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
                        out_hel, prm);
-  } else if (mode == ME_MODE_MIXED && P::NCOLOR >= 6 && P::NCOLOR <= 32) {
+  } else if ((mode == ME_MODE_MIXED || mode == ME_MODE_MIXED_MFMA32) && P::NCOLOR >= 6 && P::NCOLOR <= 32) {
     if (out_hel || !out) return -1;
-    hipLaunchKernelGGL((me_kernel_mfma<P>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out, prm);
-  } else if (mode == ME_MODE_MIXED || mode == ME_MODE_MIXED_VALU) {
+    if (mode == ME_MODE_MIXED)
+      hipLaunchKernelGGL((me_kernel_mfma<P, false>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
+                         prm);
+    else
+      hipLaunchKernelGGL((me_kernel_mfma<P, true>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
+                         prm);
+  } else if (mode == ME_MODE_MIXED || mode == ME_MODE_MIXED_VALU || mode == ME_MODE_MIXED_MFMA32) {
     if (out_hel) return -1;
     hipLaunchKernelGGL((me_kernel<P, float>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
                        nullptr, prm);

@@ -47,6 +47,7 @@ FLOPS = {
     "ffv_fin": 154, "ffv_fout": 154, "ffv_v0": 144, "ffv_vm": 170,
     "vvv_v": 158, "vvvv_acc": 132,
     "amp_ffv": 98, "amp_vvv": 168, "amp_vvvv_acc": 150,
+    "ffv_half_row": 64, "ffv_half_col": 64, "amp_dot": 30,
     "ffv_v0_ew": 144, "ffv_vm_ew": 170, "amp_ffv_ew": 98, "amp_ffv_ew_acc": 100,
 }
 # momentum sum per extra leg, and the propagator factor per kind
@@ -234,7 +235,7 @@ def _ordered_partitions(S):
                 yield (block,) + tail
 
 
-def qcd_program(ng: int) -> Program:
+def qcd_program(ng: int, share_half: bool = True) -> Program:
     """g g > t t~ + (ng-2) g.  Gluon g sits on leg 0, 1, 4, 5, ... ."""
     gl = [0, 1] + [4 + i for i in range(ng - 2)]
     T, TB = 2, 3
@@ -355,13 +356,61 @@ def qcd_program(ng: int) -> Program:
             ops = [Op("amp_ffv", a, [row(seq[:j - 1]), tree(seq[j - 1]), col(seq[j:])], {})]
         ops = [add_kinematics(prog, op) for op in ops]
         ops.append(Op("jamp", None, [a], {"jam": jam}))
+        prog.items.append(ops)
+    if share_half:
+        share_half_contractions(prog, define)
+    items = []
+    for ops in prog.items:
+        amps = {op.out for op in ops if op.kind.startswith("amp")}
         deps = []
         for op in ops:
             for v in op.ins:
-                if v != a and v not in deps:
+                if v not in amps and v not in deps:
                     deps.append(v)
-        prog.items.append((ops, deps))
+        items.append((ops, deps))
+    prog.items = items
     return prog
+
+
+def share_half_contractions(prog, define):
+    """Amplitudes rbar (gamma.J) psi that share (rbar, J) or (J, psi) compute
+    the shared half contraction once (64 flop) and finish with a 4-component
+    dot (30 flop) instead of a full vertex (98 flop) each."""
+    amps = [ops[0] for ops in prog.items if ops[0].kind == "amp_ffv"]
+    by_rj, by_jc = {}, {}
+    for o in amps:
+        by_rj[(o.ins[0], o.ins[1])] = by_rj.get((o.ins[0], o.ins[1]), 0) + 1
+        by_jc[(o.ins[1], o.ins[2])] = by_jc.get((o.ins[1], o.ins[2]), 0) + 1
+    names = {}
+    groups = {}     # half contraction -> position of its merged item
+    merged = []
+    for ops in prog.items:
+        o = ops[0]
+        if o.kind != "amp_ffv":
+            merged.append(ops)
+            continue
+        r, J, c = o.ins[:3]
+        n_rj, n_jc = by_rj[(r, J)], by_jc[(J, c)]
+        if max(n_rj, n_jc) < 2:
+            merged.append(ops)
+            continue
+        if n_rj >= n_jc:
+            key = ("row", r, J)
+            if key not in names:
+                names[key] = define(f"H{len(names)}", [Op("ffv_half_row", f"H{len(names)}", [r, J], {})])
+            ops[0] = Op("amp_dot", o.out, [names[key], c], {})
+        else:
+            key = ("col", J, c)
+            if key not in names:
+                names[key] = define(f"H{len(names)}", [Op("ffv_half_col", f"H{len(names)}", [J, c], {})])
+            ops[0] = Op("amp_dot", o.out, [r, names[key]], {})
+        # amplitudes sharing a half contraction form one scheduling item
+        if key in groups:
+            merged[groups[key]] = merged[groups[key]] + ops
+        else:
+            groups[key] = len(merged)
+            merged.append(ops)
+    prog.items = merged
 
 
 # --------------------------------------------------------------- ee -> mumu
@@ -403,7 +452,26 @@ def _closure(prog, names):
     return seen
 
 
-def schedule(prog: Program, budget: int) -> Program:
+def schedule(prog: Program, budget: int, iters: int = 4) -> Program:
+    """Best of ``iters`` greedy passes, each starting from the amplitude
+    order the previous pass chose (fewest executed flops wins)."""
+    items = prog.items
+    best = None
+    start = list(range(len(items)))
+    for _ in range(max(1, iters)):
+        prog.items = [items[i] for i in start]
+        _schedule_once(prog, budget)
+        order = [start[i] for i in prog.order]
+        f = prog.executed_flops_per_helicity()
+        if best is None or f < best[0]:
+            best = (f, prog.ops, order)
+        start = order
+    prog.items = items
+    prog.ops, prog.order = best[1], best[2]
+    return prog
+
+
+def _schedule_once(prog: Program, budget: int) -> Program:
     """Linearise the DAG for one lane with at most ``budget`` live register
     dwords of cached values (FP64 sizes; recomputing evicted ones).
     Amplitudes are taken greedily:

@@ -418,3 +418,17 @@ def test_rambo_kinematics(cfg):
     c = p[:, 2:, 3] / np.linalg.norm(p[:, 2:, 1:], axis=-1)
     assert abs(c.mean()) < 5 / math.sqrt(c.size)
     assert np.array_equal(config_events(cfg, 10), p[:10])
+
+
+def test_max_weight_bruteforce(oracle_lib):
+    """The unweighting step's definition checked element by element with a
+    plain loop on a small batch (including a negative factor and a NaN)."""
+    me = [1.5, 2.0, float("nan"), 0.25, 7.0]
+    f = [2.0, -1.0, 3.0, 8.0, 0.5]
+    w, m = oracle_lib.max_weight(me, f)
+    expect = []
+    for a, b in zip(me, f):
+        x = a * b
+        expect.append(x if x > 0 else 0.0)
+    assert list(w) == expect and m == max(expect) == 3.5
+    assert oracle_lib.max_weight([], [])[1] == 0.0

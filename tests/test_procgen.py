@@ -74,12 +74,14 @@ def _gellmann():
     return l / 2
 
 
-@pytest.mark.parametrize("ng,items", [(2, 3), (3, 15), (4, 105), (5, 945)])
-def test_program_items(ng, items):
+@pytest.mark.parametrize("ng,amps", [(2, 3), (3, 15), (4, 105), (5, 945)])
+def test_program_items(ng, amps):
     """One amplitude per (sequence of binary trees) on the top line; the
     four-gluon pieces are folded into the trees."""
-    p = program.qcd_program(ng)
-    assert len(p.items) == items
+    for share in (False, True):
+        p = program.qcd_program(ng, share_half=share)
+        n = sum(1 for ops, _ in p.items for op in ops if op.kind == "jamp")
+        assert n == amps
 
 
 @pytest.mark.parametrize("budget", [128, 256, 320, 512])
@@ -91,6 +93,7 @@ def test_schedule_is_valid(ng, budget):
     program.schedule(p, budget)
     defined = set()
     jamps = 0
+    n_amps = sum(1 for ops, _ in p.items for op in ops if op.kind == "jamp")
     for op in p.ops:
         for v in op.ins:
             if op.kind in ("vvvv_acc", "amp_vvvv_acc", "amp_ffv_ew_acc") and v == op.out:
@@ -99,10 +102,12 @@ def test_schedule_is_valid(ng, budget):
         if op.out:
             base = re.sub(r"_r\d+$", "", op.out)
             assert base in p.values or base.startswith("a")
+            assert not (op.kind.startswith("amp") and op.out in defined and op.kind != "amp_vvvv_acc"
+                        and op.kind != "amp_ffv_ew_acc"), "amplitude computed twice"
             defined.add(op.out)
         if op.kind == "jamp":
             jamps += 1
-    assert jamps == len(p.items)
+    assert jamps == n_amps
     # the inputs one vertex call needs at once may briefly exceed a tiny budget
     assert program.peak_live(p) <= budget + 96
 
