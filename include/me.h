@@ -156,6 +156,18 @@ const char* me_last_error(void);
 me_status me_max_weight(const double* d_me, const double* d_factor, int64_t nevt, double* d_w,
                         double* d_max, void* hip_stream);
 
+/* Device-side phase-space generation: nevt RAMBO events (Kleiss, Stirling,
+ * Ellis), the flat generator of the paper's standalone test-bed (Sec. 2),
+ * written to d_momenta [nevt][nfinal+2][4] (device) in the layout me_compute
+ * reads: two massless beams (sqrt_s/2)(1,0,0,+-1), then nfinal (2..5) final
+ * particles with masses[0..nfinal) (host array, GeV).  Random numbers from
+ * Philox4x32-10 with key = seed and counter = (event, 2*particle+half): the
+ * batch is reproducible and any event range can be regenerated.  Asynchronous
+ * on hip_stream; nothing is allocated.  ME_EINVAL for bad sizes or
+ * sum(masses) >= sqrt_s. */
+me_status me_rambo(int64_t nevt, int32_t nfinal, const double* masses, double sqrt_s, uint64_t seed,
+                   double* d_momenta, void* hip_stream);
+
 /* ------------------------------------------------------------ serving --
  * A persistent request loop for uneven |M|^2 batches of several processes,
  * as integration channels emit them (continuous batching).  Requests are

@@ -85,6 +85,8 @@ def lib():
         L.oracle_dressed_amp.argtypes = [i, P(Params), P(d), i, P(i), P(d)]
         L.oracle_colour_basis.argtypes = [i, P(i), P(d)]
         L.oracle_colour_matrix.argtypes = [i, P(d)]
+        L.oracle_uniforms.argtypes = [ctypes.c_int64, i, ctypes.c_uint64, P(d)]
+        L.oracle_rambo.argtypes = [ctypes.c_int64, i, P(d), d, ctypes.c_uint64, P(d)]
         _lib = L
     return _lib
 
@@ -185,3 +187,20 @@ def max_weight(me_values, factors):
     w = np.asarray(me_values, dtype=np.float64) * np.asarray(factors, dtype=np.float64)
     w = np.where(w > 0, w, 0.0)
     return w, (float(w.max()) if w.size else 0.0)
+
+
+def uniforms(nevt, nfinal, seed):
+    """Philox4x32-10 uniforms of the device phase-space generator, [nevt][nfinal][4]."""
+    out = np.empty((nevt, nfinal, 4), dtype=np.float64)
+    if lib().oracle_uniforms(int(nevt), int(nfinal), int(seed), _dp(out)) != 0:
+        raise ValueError("oracle_uniforms failed")
+    return out
+
+
+def rambo(nevt, masses, sqrt_s, seed):
+    """RAMBO momenta from the Philox stream, [nevt][nfinal+2][4]."""
+    m = np.ascontiguousarray(masses, dtype=np.float64)
+    out = np.empty((nevt, m.size + 2, 4), dtype=np.float64)
+    if lib().oracle_rambo(int(nevt), int(m.size), _dp(m), float(sqrt_s), int(seed), _dp(out)) != 0:
+        raise ValueError("oracle_rambo failed")
+    return out

@@ -668,9 +668,129 @@ void run_me(int proc, const oracle_params* prm, const double* mom, int64_t nevt,
   }
 }
 
+// ------------------------------------------------------ phase-space points
+// Counter-based random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw,
+// "Parallel random numbers: as easy as 1, 2, 3", SC'11), written from its
+// definition: ten rounds of a multiply-xor network on a 128-bit counter with
+// a 64-bit key bumped by the golden-ratio Weyl constants between rounds.
+struct Ctr { uint32_t v[4]; };
+Ctr philox(Ctr c, uint32_t k0, uint32_t k1) {
+  const uint64_t M0 = 0xD2511F53ull, M1 = 0xCD9E8D57ull;
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    const uint64_t p0 = M0 * c.v[0], p1 = M1 * c.v[2];
+    Ctr d;
+    d.v[0] = uint32_t(p1 >> 32) ^ c.v[1] ^ k0;
+    d.v[1] = uint32_t(p1);
+    d.v[2] = uint32_t(p0 >> 32) ^ c.v[3] ^ k1;
+    d.v[3] = uint32_t(p0);
+    c = d;
+  }
+  return c;
+}
+// 53-bit uniform in [0, 1) from two 32-bit words
+double unit53(uint32_t a, uint32_t b) {
+  return double((uint64_t(a >> 5) << 26) | uint64_t(b >> 6)) / 9007199254740992.0;
+}
+// the four uniforms (cos theta, phi, energy factors) of final particle i of event e
+void event_uniforms(int64_t e, int i, uint64_t seed, double* u) {
+  const uint32_t k0 = uint32_t(seed), k1 = uint32_t(seed >> 32);
+  for (int half = 0; half < 2; ++half) {
+    Ctr c{{uint32_t(e), uint32_t(uint64_t(e) >> 32), uint32_t(2 * i + half), 0u}};
+    Ctr r = philox(c, k0, k1);
+    u[2 * half] = unit53(r.v[0], r.v[1]);
+    u[2 * half + 1] = unit53(r.v[2], r.v[3]);
+  }
+}
+
+// RAMBO (Kleiss, Stirling, Ellis 1986) for one event, in double, with the
+// massless invariant mass as sum_{i<j} q0_i q0_j |n_i - n_j|^2, a two-body
+// final state rebuilt back to back along RAMBO's direction, and Newton's
+// method for massive final states.
+void rambo_event(int64_t e, int n, const double* mass, double sqrt_s, uint64_t seed, double* out) {
+  const double pi = std::acos(-1.0);
+  std::vector<double> q0(n), nh(3 * n), p(4 * n);
+  for (int i = 0; i < n; ++i) {
+    double u[4];
+    event_uniforms(e, i, seed, u);
+    const double c = 2 * u[0] - 1, phi = 2 * pi * u[1];
+    q0[i] = -std::log((1 - u[2]) * (1 - u[3]));
+    const double st = std::sqrt(std::max(0.0, 1 - c * c));
+    nh[3 * i] = st * std::cos(phi);
+    nh[3 * i + 1] = st * std::sin(phi);
+    nh[3 * i + 2] = c;
+  }
+  double Q[4] = {0, 0, 0, 0}, M2 = 0;
+  for (int i = 0; i < n; ++i) {
+    Q[0] += q0[i];
+    for (int k = 0; k < 3; ++k) Q[k + 1] += q0[i] * nh[3 * i + k];
+    for (int j = i + 1; j < n; ++j) {
+      double d2 = 0;
+      for (int k = 0; k < 3; ++k) d2 += (nh[3 * i + k] - nh[3 * j + k]) * (nh[3 * i + k] - nh[3 * j + k]);
+      M2 += q0[i] * q0[j] * d2;
+    }
+  }
+  const double M = std::sqrt(M2), gam = Q[0] / M, a = 1 / (1 + gam), x = sqrt_s / M;
+  const double b[3] = {-Q[1] / M, -Q[2] / M, -Q[3] / M};
+  for (int i = 0; i < n; ++i) {
+    double qv[3], bq = 0;
+    for (int k = 0; k < 3; ++k) { qv[k] = q0[i] * nh[3 * i + k]; bq += b[k] * qv[k]; }
+    p[4 * i] = x * (gam * q0[i] + bq);
+    for (int k = 0; k < 3; ++k) p[4 * i + 1 + k] = x * (qv[k] + b[k] * q0[i] + a * bq * b[k]);
+  }
+  if (n == 2) {
+    const double pn = std::sqrt(p[1] * p[1] + p[2] * p[2] + p[3] * p[3]);
+    const double e1 = (sqrt_s * sqrt_s + mass[0] * mass[0] - mass[1] * mass[1]) / (2 * sqrt_s);
+    const double pa = std::sqrt(std::max(0.0, e1 * e1 - mass[0] * mass[0]));
+    double dir[3] = {p[1] / pn, p[2] / pn, p[3] / pn};
+    p[0] = e1;
+    p[4] = sqrt_s - e1;
+    for (int k = 0; k < 3; ++k) { p[1 + k] = pa * dir[k]; p[5 + k] = -pa * dir[k]; }
+  } else {
+    double msum = 0;
+    for (int i = 0; i < n; ++i) msum += mass[i];
+    if (msum > 0) {
+      double xi = std::sqrt(1 - (msum / sqrt_s) * (msum / sqrt_s));
+      for (int it = 0; it < 30; ++it) {
+        double f = -sqrt_s, df = 0;
+        for (int i = 0; i < n; ++i) {
+          const double en = std::sqrt(mass[i] * mass[i] + xi * xi * p[4 * i] * p[4 * i]);
+          f += en;
+          df += xi * p[4 * i] * p[4 * i] / en;
+        }
+        if (std::fabs(f) <= 4e-16 * sqrt_s) break;
+        xi -= f / df;
+      }
+      for (int i = 0; i < n; ++i) {
+        p[4 * i] = std::sqrt(mass[i] * mass[i] + xi * xi * p[4 * i] * p[4 * i]);
+        for (int k = 1; k < 4; ++k) p[4 * i + k] *= xi;
+      }
+    }
+  }
+  const double h = sqrt_s / 2;
+  const double beams[8] = {h, 0, 0, h, h, 0, 0, -h};
+  std::memcpy(out, beams, sizeof(beams));
+  std::memcpy(out + 8, p.data(), sizeof(double) * 4 * n);
+}
+
 }  // namespace
 
 extern "C" {
+
+int oracle_uniforms(int64_t nevt, int nfinal, uint64_t seed, double* out) {
+  if (nevt < 0 || nfinal < 1 || (nevt > 0 && !out)) return -1;
+  for (int64_t e = 0; e < nevt; ++e)
+    for (int i = 0; i < nfinal; ++i) event_uniforms(e, i, seed, out + (e * nfinal + i) * 4);
+  return 0;
+}
+
+int oracle_rambo(int64_t nevt, int nfinal, const double* masses, double sqrt_s, uint64_t seed, double* out) {
+  if (nevt < 0 || nfinal < 2 || nfinal > 5 || !masses || (nevt > 0 && !out)) return -1;
+#pragma omp parallel for schedule(static)
+  for (int64_t e = 0; e < nevt; ++e) rambo_event(e, nfinal, masses, sqrt_s, seed, out + e * 4 * (nfinal + 2));
+  return 0;
+}
+
 
 int oracle_npar(int proc) { return npar_of(proc); }
 int oracle_ncolor(int proc) { return proc == 0 ? 1 : (npar_of(proc) < 0 ? -1 : int(factorial(ngluon_of(proc)))); }

@@ -87,6 +87,13 @@ int oracle_colour_basis(int ngluons, const int* colours, double* out);
  * force over explicit Gell-Mann matrices, out[n!][n!]. */
 int oracle_colour_matrix(int ngluons, double* out);
 
+/* Phase-space points with counter-based random numbers (Philox4x32-10):
+ * the four uniforms per final particle (cos theta, phi, two energy factors),
+ * out[nevt][nfinal][4], and RAMBO momenta out[nevt][nfinal+2][4] (beams on
+ * +-z at sqrt_s/2 each). */
+int oracle_uniforms(int64_t nevt, int nfinal, uint64_t seed, double* out);
+int oracle_rambo(int64_t nevt, int nfinal, const double* masses, double sqrt_s, uint64_t seed, double* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -78,7 +78,7 @@ EXPORTS = [
     "me_default_params", "me_create", "me_helicity_filter", "me_compute", "me_compute_helicities",
     "me_good_helicities", "me_info", "me_destroy", "me_last_error",
     "me_server_create", "me_server_submit", "me_server_poll", "me_server_wait", "me_server_stats",
-    "me_server_destroy", "me_max_weight",
+    "me_server_destroy", "me_max_weight", "me_rambo",
 ]
 
 _lib = None
@@ -106,6 +106,7 @@ def lib():
             if name not in ("me_default_params", "me_last_error") and hasattr(L, name):
                 getattr(L, name).restype = i32
         L.me_max_weight.argtypes = [vp, vp, i64, vp, vp, vp]
+        L.me_rambo.argtypes = [i64, i32, P(d), d, ctypes.c_uint64, vp, vp]
         if hasattr(L, "me_server_create"):
             L.me_server_create.argtypes = [i64, i32, P(vp)]
             L.me_server_submit.argtypes = [vp, vp, vp, i64, vp, P(i64)]
@@ -171,6 +172,14 @@ def me_max_weight(d_me: int, d_factor: int, nevt: int, d_w: int, d_max: int, str
     """Device pointers in; *d_max receives max_i(me_i * factor_i)."""
     _check(lib().me_max_weight(d_me or None, d_factor or None, nevt, d_w or None, d_max or None, stream or None),
            "me_max_weight")
+
+
+def me_rambo(nevt: int, masses, sqrt_s: float, seed: int, d_momenta: int, stream: int = 0) -> None:
+    """Device RAMBO: nevt events with final-state masses `masses` into the
+    device buffer d_momenta [nevt][len(masses)+2][4]."""
+    m = (ctypes.c_double * len(masses))(*[float(x) for x in masses])
+    _check(lib().me_rambo(int(nevt), len(masses), m, float(sqrt_s), int(seed), d_momenta or None, stream or None),
+           "me_rambo")
 
 
 def me_last_error() -> str:

@@ -67,7 +67,7 @@ def build(processes=None, jobs=None, verbose=True) -> str:
     table = os.path.join(GEN, "process_table.inc")
     units = [(s, hdrs + [s.replace(".hip", "_proc.inc")]) for s in srcs]
     units.append((os.path.join(CSRC, "runtime.cpp"), hdrs + [table, os.path.join(ROOT, "include", "me.h")]))
-    for extra in ("server.cpp", "unweight.cpp"):
+    for extra in ("server.cpp", "unweight.cpp", "rambo.cpp"):
         units.append((os.path.join(CSRC, extra),
                       hdrs + [os.path.join(CSRC, "server_core.hpp"), os.path.join(ROOT, "include", "me.h")]))
     jobs = jobs or min(len(units), os.cpu_count() or 4)

@@ -1,0 +1,158 @@
+// Device-side phase-space generation: RAMBO (Kleiss, Stirling, Ellis 1986),
+// the generator of the paper's standalone test-bed (Sec. 2), writing momenta
+// straight into the [nevt][npar][4] layout me_compute reads, so a batch never
+// crosses PCIe.  One event per lane; HBM-write bound (32 npar bytes per event).
+//
+// Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten
+// rounds of  (c0,c1,c2,c3) -> (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1,
+// lo(M0 c0))  with M0 = 0xD2511F53, M1 = 0xCD9E8D57 and the key bumped by the
+// Weyl constants (0x9E3779B9, 0xBB67AE85) between rounds.  Counter = (event
+// low, event high, 2*particle + half, 0), key = seed; one block gives two
+// 53-bit uniforms u in [0,1).  Draw order per particle: cos theta, phi, then
+// the two factors of the energy; 1-u enters the logarithms.
+//
+// Kinematics in FP64 with the massless invariant mass formed as
+// sum_{i<j} q0_i q0_j |n_i - n_j|^2 (no cancellation); a two-body final state
+// is rebuilt back to back from RAMBO's direction; massive final states are
+// rescaled with Newton's method (at most 30 steps).
+#include <hip/hip_runtime.h>
+
+#include "me.h"
+
+namespace {
+
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) { k0 += W0; k1 += W1; }
+    const uint32_t lo0 = M0 * c.x, hi0 = __umulhi(M0, c.x);
+    const uint32_t lo1 = M1 * c.z, hi1 = __umulhi(M1, c.z);
+    c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+  }
+  return c;
+}
+
+__device__ __forceinline__ double u53(uint32_t a, uint32_t b) {
+  return double((uint64_t(a >> 5) << 26) | uint64_t(b >> 6)) * (1.0 / 9007199254740992.0);
+}
+
+constexpr int kMaxFinal = 5;
+
+struct RamboArgs {
+  int32_t nfinal;
+  double sqrt_s;
+  double mass[kMaxFinal];
+  uint32_t k0, k1;
+};
+
+__global__ __launch_bounds__(256) void rambo_kernel(int64_t nevt, RamboArgs a, double* __restrict__ out) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= nevt) return;
+  const int n = a.nfinal;
+  const double pi = 3.14159265358979323846;
+  double q0[kMaxFinal], nh[kMaxFinal][3];
+  for (int i = 0; i < n; ++i) {
+    const U4 r0 = philox4x32_10(U4{uint32_t(e), uint32_t(uint64_t(e) >> 32), uint32_t(2 * i), 0u}, a.k0, a.k1);
+    const U4 r1 = philox4x32_10(U4{uint32_t(e), uint32_t(uint64_t(e) >> 32), uint32_t(2 * i + 1), 0u}, a.k0, a.k1);
+    const double c = 2.0 * u53(r0.x, r0.y) - 1.0;
+    const double phi = 2.0 * pi * u53(r0.z, r0.w);
+    q0[i] = -log((1.0 - u53(r1.x, r1.y)) * (1.0 - u53(r1.z, r1.w)));
+    const double st = sqrt(fmax(0.0, 1.0 - c * c));
+    nh[i][0] = st * cos(phi);
+    nh[i][1] = st * sin(phi);
+    nh[i][2] = c;
+  }
+  double Q[4] = {0, 0, 0, 0};
+  for (int i = 0; i < n; ++i) {
+    Q[0] += q0[i];
+    for (int k = 0; k < 3; ++k) Q[k + 1] += q0[i] * nh[i][k];
+  }
+  double M2 = 0.0;
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j) {
+      double d2 = 0.0;
+      for (int k = 0; k < 3; ++k) {
+        const double d = nh[i][k] - nh[j][k];
+        d2 += d * d;
+      }
+      M2 += q0[i] * q0[j] * d2;
+    }
+  const double M = sqrt(M2);
+  const double b[3] = {-Q[1] / M, -Q[2] / M, -Q[3] / M};
+  const double gam = Q[0] / M, aa = 1.0 / (1.0 + gam), x = a.sqrt_s / M;
+  double p[kMaxFinal][4];
+  for (int i = 0; i < n; ++i) {
+    double qv[3];
+    for (int k = 0; k < 3; ++k) qv[k] = q0[i] * nh[i][k];
+    const double bq = b[0] * qv[0] + b[1] * qv[1] + b[2] * qv[2];
+    p[i][0] = x * (gam * q0[i] + bq);
+    for (int k = 0; k < 3; ++k) p[i][k + 1] = x * (qv[k] + b[k] * q0[i] + aa * bq * b[k]);
+  }
+  if (n == 2) {
+    // exact back-to-back pair along RAMBO's direction
+    const double pn = sqrt(p[0][1] * p[0][1] + p[0][2] * p[0][2] + p[0][3] * p[0][3]);
+    const double m1 = a.mass[0], m2 = a.mass[1], s = a.sqrt_s;
+    const double e1 = (s * s + m1 * m1 - m2 * m2) / (2.0 * s);
+    const double pa = sqrt(fmax(0.0, e1 * e1 - m1 * m1));
+    double dir[3];
+    for (int k = 0; k < 3; ++k) dir[k] = p[0][k + 1] / pn;
+    p[0][0] = e1;
+    p[1][0] = s - e1;
+    for (int k = 0; k < 3; ++k) { p[0][k + 1] = pa * dir[k]; p[1][k + 1] = -pa * dir[k]; }
+  } else {
+    double msum = 0.0;
+    for (int i = 0; i < n; ++i) msum += a.mass[i];
+    if (msum > 0.0) {
+      double xi = sqrt(1.0 - (msum / a.sqrt_s) * (msum / a.sqrt_s));
+      for (int it = 0; it < 30; ++it) {
+        double f = -a.sqrt_s, df = 0.0;
+        for (int i = 0; i < n; ++i) {
+          const double en = sqrt(a.mass[i] * a.mass[i] + xi * xi * p[i][0] * p[i][0]);
+          f += en;
+          df += xi * p[i][0] * p[i][0] / en;
+        }
+        if (fabs(f) <= 4e-16 * a.sqrt_s) break;
+        xi -= f / df;
+      }
+      for (int i = 0; i < n; ++i) {
+        p[i][0] = sqrt(a.mass[i] * a.mass[i] + xi * xi * p[i][0] * p[i][0]);
+        for (int k = 1; k < 4; ++k) p[i][k] *= xi;
+      }
+    }
+  }
+  double* o = out + e * (4 * (n + 2));
+  const double h = 0.5 * a.sqrt_s;
+  o[0] = h; o[1] = 0.0; o[2] = 0.0; o[3] = h;
+  o[4] = h; o[5] = 0.0; o[6] = 0.0; o[7] = -h;
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < 4; ++k) o[8 + 4 * i + k] = p[i][k];
+}
+
+}  // namespace
+
+extern "C" me_status me_rambo(int64_t nevt, int32_t nfinal, const double* masses, double sqrt_s, uint64_t seed,
+                              double* d_momenta, void* hip_stream) {
+  if (nevt < 0 || nfinal < 2 || nfinal > kMaxFinal || !masses || !(sqrt_s > 0) || (nevt > 0 && !d_momenta))
+    return ME_EINVAL;
+  RamboArgs a;
+  a.nfinal = nfinal;
+  a.sqrt_s = sqrt_s;
+  double msum = 0.0;
+  for (int i = 0; i < kMaxFinal; ++i) a.mass[i] = i < nfinal ? masses[i] : 0.0;
+  for (int i = 0; i < nfinal; ++i) {
+    if (!(masses[i] >= 0)) return ME_EINVAL;
+    msum += masses[i];
+  }
+  if (msum >= sqrt_s) return ME_EINVAL;
+  a.k0 = uint32_t(seed);
+  a.k1 = uint32_t(seed >> 32);
+  if (nevt == 0) return ME_OK;
+  const int64_t blocks = (nevt + 255) / 256;
+  if (blocks > 0x7fffffffLL) return ME_EINVAL;
+  hipLaunchKernelGGL(rambo_kernel, dim3(unsigned(blocks)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), nevt,
+                     a, d_momenta);
+  return hipGetLastError() == hipSuccess ? ME_OK : ME_EHIP;
+}

@@ -432,3 +432,45 @@ def test_max_weight_bruteforce(oracle_lib):
         expect.append(x if x > 0 else 0.0)
     assert list(w) == expect and m == max(expect) == 3.5
     assert oracle_lib.max_weight([], [])[1] == 0.0
+
+
+# ------------------------------------------------- device phase-space pins
+class _FixedUniforms:
+    """numpy.random.Generator stand-in that hands out given uniforms."""
+
+    def __init__(self, u):
+        self.u = u
+
+    def random(self, shape):
+        assert tuple(shape) == self.u.shape
+        return self.u
+
+
+@pytest.mark.parametrize("masses,sqs", [([0.0, 0.0], 500.0), ([173.0, 173.0], 1500.0),
+                                        ([173.0, 173.0, 0.0], 1500.0), ([173.0, 173.0, 0.0, 0.0], 1500.0),
+                                        ([173.0, 173.0, 0.0, 0.0, 0.0], 1500.0)])
+def test_philox_rambo_matches_extended_precision_rambo(oracle_lib, masses, sqs):
+    """The oracle's double-precision RAMBO equals the extended-precision RAMBO
+    of the input module fed with the same uniforms."""
+    n = 4000
+    u = oracle_lib.uniforms(n, len(masses), seed=9)
+    ref = rambo(n, sqs, masses, seed=0, rng=_FixedUniforms(u))
+    got = oracle_lib.rambo(n, masses, sqs, seed=9)
+    rel = np.abs(got - ref).max(axis=(1, 2)) / sqs
+    assert np.median(rel) < 1e-15 and rel.max() < 1e-11
+
+
+def test_philox_uniformity(oracle_lib):
+    """Philox4x32-10 stream: uniform on [0,1) (chi-square over 64 bins for
+    each of the four draws per particle) and uncorrelated across draws."""
+    u = oracle_lib.uniforms(1 << 14, 5, seed=123).reshape(-1, 4)
+    assert u.min() >= 0 and u.max() < 1
+    for k in range(4):
+        h, _ = np.histogram(u[:, k], bins=64, range=(0, 1))
+        exp = u.shape[0] / 64
+        chi2 = ((h - exp) ** 2 / exp).sum()
+        assert chi2 < 63 + 5 * math.sqrt(2 * 63)
+    c = np.corrcoef(u.T)
+    assert np.abs(c - np.eye(4)).max() < 0.03
+    # different seeds and counters give different streams
+    assert not np.array_equal(oracle_lib.uniforms(8, 2, 1), oracle_lib.uniforms(8, 2, 2))
