@@ -134,6 +134,38 @@ def main():
                           "kernel": "me_kernel<Proc_ggttgg, double>", "kernel_ms": t_launch64 * 1e3},
     }
 
+    # HBM-bound neighbours of the path: device phase-space generation and the
+    # batch-unweighting reduction, timed with events on the current stream
+    stream = torch.cuda.current_stream().cuda_stream
+    masses = [173.0, 173.0, 0.0, 0.0]
+    d_gen = torch.empty((n, 6, 4), dtype=torch.float64, device=dev)
+
+    def t_events(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) * 1e-3 / reps
+
+    t_rambo = t_events(lambda: B.me_rambo(n, masses, 1500.0, 4, d_gen.data_ptr(), stream))
+    fac = torch.rand(n, dtype=torch.float64, device=dev)
+    w = torch.empty(n, dtype=torch.float64, device=dev)
+    mx = torch.empty(1, dtype=torch.float64, device=dev)
+    t_maxw = t_events(lambda: B.me_max_weight(out32.data_ptr(), fac.data_ptr(), n, w.data_ptr(), mx.data_ptr(),
+                                              stream))
+    HBM = 8e12
+    rec["device_rambo"] = {"events_per_s": n / t_rambo, "ms": t_rambo * 1e3,
+                           "roofline": {"bound": "hbm", "achieved": n * 6 * 32 / t_rambo / 1e9, "peak": HBM / 1e9,
+                                        "unit": "GB/s", "frac": n * 6 * 32 / t_rambo / HBM,
+                                        "bytes_per_event": 192}}
+    rec["max_weight"] = {"events_per_s": n / t_maxw, "ms": t_maxw * 1e3,
+                         "roofline": {"bound": "hbm", "achieved": n * 24 / t_maxw / 1e9, "peak": HBM / 1e9,
+                                      "unit": "GB/s", "frac": n * 24 / t_maxw / HBM, "bytes_per_event": 24}}
+
     if not args.no_cpu:
         cb, ref, ncpu = cpu_baseline(mom_np)
         rec["cpu_baseline"] = cb
