@@ -23,8 +23,7 @@ GEN = os.path.join(CSRC, "gen")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libme_mi355x.so")
 
-# ggttggg (1240 diagrams) is generated on request only: see the design doc.
-PROCESSES = ["eemumu", "ggtt", "ggttg", "ggttgg"]
+PROCESSES = ["eemumu", "ggtt", "ggttg", "ggttgg", "ggttggg"]
 
 HIPCC = os.environ.get("HIPCC", "hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -63,9 +62,11 @@ def build(processes=None, jobs=None, verbose=True) -> str:
     from paper_2312_02898_amd.procgen import codegen
     procs = processes or PROCESSES
     srcs = codegen.generate(GEN, names=procs)
-    hdrs = [os.path.join(CSRC, f) for f in ("helas.hpp", "kernels.hpp", "me_types.h")]
+    hdrs = [os.path.join(CSRC, f) for f in ("helas.hpp", "kernels.hpp", "me_types.h", "colour_mfma.hpp", "split.hpp")]
     table = os.path.join(GEN, "process_table.inc")
-    units = [(s, hdrs + [s.replace(".hip", "_proc.inc")]) for s in srcs]
+    # a part kernel of a split process, <name>__<form>_<j>.hip, shares <name>_proc.inc
+    units = [(s, hdrs + [os.path.join(GEN, os.path.basename(s)[:-4].split("__")[0] + "_proc.inc")])
+             for s in srcs]
     units.append((os.path.join(CSRC, "runtime.cpp"), hdrs + [table, os.path.join(ROOT, "include", "me.h")]))
     for extra in ("server.cpp", "unweight.cpp", "rambo.cpp"):
         units.append((os.path.join(CSRC, extra),

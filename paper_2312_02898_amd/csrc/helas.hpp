@@ -345,6 +345,27 @@ __device__ __forceinline__ double opaque_d(double x) {
   asm volatile("" : "+v"(x));
   return x;
 }
+// Pins a jamp accumulator update where the schedule put it.  Without it the
+// optimizer sinks the (pure) additions down to the accumulator's last use,
+// which keeps every amplitude alive until then.
+template <class T> __device__ __forceinline__ void hold(cx<T>& a) {
+  asm volatile("" : "+v"(a.r), "+v"(a.i));
+}
+template <class T, int N> __device__ __forceinline__ void hold_jamp(cx<T> (&jamp)[N], int k) { hold(jamp[k]); }
+// jamps kept in memory are not sunk
+template <class J> __device__ __forceinline__ void hold_jamp(J&, int) {}
+
+// A momentum copy the compiler cannot identify with the original, for
+// recomputed external wavefunctions (which have no wavefunction input).
+struct OpaqueMom {
+  double v[4];
+};
+__device__ __forceinline__ OpaqueMom opaque_mom(const double* p) {
+  OpaqueMom r;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) r.v[c] = opaque_d(p[c]);
+  return r;
+}
 template <class T> __device__ __forceinline__ void acc_scaled(wf<T>& o, const wf<T>& v, T s) {
   for (int m = 0; m < 4; ++m) o.c[m] = o.c[m] + s * v.c[m];
 }

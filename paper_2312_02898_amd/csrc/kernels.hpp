@@ -14,6 +14,7 @@
 #include "colour_mfma.hpp"
 #include "helas.hpp"
 #include "me_types.h"
+#include "split.hpp"
 
 namespace me {
 
@@ -53,6 +54,47 @@ __global__ __launch_bounds__(256) void me_kernel(const double* __restrict__ mom,
     cx<T> jamp[P::NCOLOR];
     P::template amplitudes<T>(p, hel, prm, jamp);
     const double q = double(P::template colour_sum<T>(jamp));
+    if (out_hel) out_hel[e * P::NHEL + hel] = q * (P::coupling_factor(prm) / P::CDEN);
+    acc += q;
+  }
+  if (out) out[e] = acc * (P::coupling_factor(prm) / (P::CDEN * P::IDEN));
+}
+
+// Jamps of one lane held in LDS instead of registers: element k of lane l at
+// base[k * 64 + l], so a wave's 64 accesses to one jamp are contiguous.
+template <class T>
+struct LdsJamps {
+  cx<T>* base;
+  __device__ __forceinline__ cx<T>& operator[](int k) const { return base[k * 64]; }
+};
+
+// FP64 form with the jamps in LDS (frees 4*NCOLOR registers per lane for the
+// wavefunction schedule).  128-thread blocks: 2 waves x NCOLOR x 64 x 16 B.
+template <class P>
+__global__ __launch_bounds__(128) void me_kernel_ldsjamp(const double* __restrict__ mom, int64_t nevt,
+                                                          double* __restrict__ out, double* __restrict__ out_hel,
+                                                          const MeParams prm) {
+  __shared__ cx<double> lds[2 * P::NCOLOR * 64];
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= nevt) return;
+  LdsJamps<double> jamp{lds + wave * P::NCOLOR * 64 + lane};
+  double p[P::NPAR][4];
+  const double2* src = reinterpret_cast<const double2*>(mom + e * (4 * P::NPAR));
+#pragma unroll
+  for (int i = 0; i < P::NPAR; ++i) {
+    const double2 a = src[2 * i], b = src[2 * i + 1];
+    p[i][0] = a.x; p[i][1] = a.y; p[i][2] = b.x; p[i][3] = b.y;
+  }
+  double acc = 0.0;
+  for (int ih = 0; ih < prm.nhel; ++ih) {
+#pragma unroll
+    for (int i = 0; i < P::NPAR; ++i)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) asm volatile("" : "+v"(p[i][c]));
+    const unsigned hel = prm.hel[ih];
+    P::template amplitudes<double>(p, hel, prm, jamp);
+    const double q = P::template colour_sum<double>(jamp);
     if (out_hel) out_hel[e * P::NHEL + hel] = q * (P::coupling_factor(prm) / P::CDEN);
     acc += q;
   }
@@ -105,13 +147,21 @@ __global__ __launch_bounds__(256) void me_kernel_mfma(const double* __restrict__
 template <class P>
 int launch(int mode, const double* mom, int64_t nevt, double* out, double* out_hel, const MeParams& prm,
            hipStream_t stream) {
+  static_assert(!P::SPLIT, "split processes launch through launch_split");
   if (nevt <= 0) return 0;
   const int block = 256;
   const int64_t nblk = (nevt + block - 1) / block;
   if (nblk > 0x7fffffffLL) return -1;
   if (mode == ME_MODE_FP64) {
-    hipLaunchKernelGGL((me_kernel<P, double>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
-                       out_hel, prm);
+    // one FP64 kernel per process, chosen when the process is generated
+    if constexpr (P::FP64_LDS_JAMPS) {
+      const int64_t nb = (nevt + 127) / 128;
+      hipLaunchKernelGGL((me_kernel_ldsjamp<P>), dim3(unsigned(nb)), dim3(128), 0, stream, mom, nevt, out,
+                         out_hel, prm);
+    } else {
+      hipLaunchKernelGGL((me_kernel<P, double>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
+                         out_hel, prm);
+    }
   } else if ((mode == ME_MODE_MIXED || mode == ME_MODE_MIXED_MFMA32) && P::NCOLOR >= 6 && P::NCOLOR <= 32) {
     if (out_hel || !out) return -1;
     if (mode == ME_MODE_MIXED)

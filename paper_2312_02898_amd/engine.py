@@ -12,6 +12,7 @@ PROCESS_NAMES = {
     "ggtt": "g g > t t~",
     "ggttg": "g g > t t~ g",
     "ggttgg": "g g > t t~ g g",
+    "ggttggg": "g g > t t~ g g g",
 }
 
 

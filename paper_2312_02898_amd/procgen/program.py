@@ -89,6 +89,10 @@ class Program:
         for op in ops:
             if op.kind == "jamp":
                 f += 2 * len(op.prm["jam"])
+            elif op.kind in ("jadd", "jflush"):
+                f += 2
+            elif op.kind == "jset":
+                pass
             elif op.kind == "kmom":
                 f += 4 * (bin(op.prm["mk"]).count("1") - 1)
             elif op.kind == "den":
@@ -135,6 +139,8 @@ def value_size(name: str) -> int:
         return 4
     if name.startswith("I"):      # real propagator factor 1/K^2
         return 2
+    if name.startswith("Q"):      # complex jamp accumulator (workspace-backed)
+        return 4
     return 16                     # complex 4-component wavefunction
 
 
@@ -489,6 +495,18 @@ def _schedule_once(prog: Program, budget: int) -> Program:
     for i in range(len(items)):
         for v in closures[i]:
             uses.setdefault(v, []).append(i)
+    # workspace-backed jamps: accumulator Q<k> is a cached value whose
+    # eviction writes it back to memory (store or read-add-store)
+    jmem = getattr(prog, "jamps_in_memory", False)
+    item_jamps = [set() for _ in items]
+    if jmem:
+        for i, (ops, _) in enumerate(items):
+            for op in ops:
+                if op.kind == "jamp":
+                    item_jamps[i] |= {f"Q{k}" for k, _ in op.prm["jam"]}
+            for q in sorted(item_jamps[i]):
+                uses.setdefault(q, []).append(i)
+                vcost[q] = JFLUSH_COST
 
     def next_use(v):
         best = len(items) + 1
@@ -507,13 +525,29 @@ def _schedule_once(prog: Program, budget: int) -> Program:
         ins = [names.get(v, cache.get(v, v)) for v in op.ins]
         return Op(op.kind, names.get(op.out, op.out) if op.out else None, ins, dict(op.prm))
 
+    jcap = getattr(prog, "jamp_capacity", None)
+
     def evict(pinned):
-        while sum(value_size(v) for v in cache) > budget:
-            cands = [v for v in cache if v not in pinned]
+        # jamp accumulators: their own capacity when one is set, else they
+        # share the register budget with the wavefunctions
+        while jcap is not None and sum(1 for v in cache if v.startswith("Q")) > jcap:
+            cands = [v for v in cache if v.startswith("Q") and v not in pinned]
+            if not cands:
+                break
+            victim = max(cands, key=next_use)
+            out.append(Op("jflush", None, [cache[victim]], {"k": int(victim[1:])}))
+            del cache[victim]
+
+        def held(v):
+            return jcap is None or not v.startswith("Q")
+        while sum(value_size(v) for v in cache if held(v)) > budget:
+            cands = [v for v in cache if v not in pinned and held(v)]
             if not cands:
                 return
             # furthest next use, weighted by footprint over recompute cost
             victim = max(cands, key=lambda v: (next_use(v) - cur[0] + 1) * value_size(v) / vcost[v])
+            if victim.startswith("Q"):
+                out.append(Op("jflush", None, [cache[victim]], {"k": int(victim[1:])}))
             del cache[victim]
 
     def ensure(v, pinned):
@@ -537,12 +571,16 @@ def _schedule_once(prog: Program, budget: int) -> Program:
         return nm
 
     def missing_cost(i):
-        return sum(vcost[v] for v in closures[i] if v not in cache)
+        c = sum(vcost[v] for v in closures[i] if v not in cache)
+        if jcap is not None and len([v for v in cache if v.startswith("Q")]) < jcap:
+            return c
+        return c + sum(JFLUSH_COST for q in item_jamps[i] if q not in cache)
 
     order = []
+    item_end = []
     cur = [0]
     while remaining:
-        i = min(remaining, key=lambda j: (missing_cost(j), j))
+        i = _pick[0](remaining, lambda j: (missing_cost(j), j))
         cur[0] = i
         remaining.discard(i)
         order.append(i)
@@ -552,13 +590,93 @@ def _schedule_once(prog: Program, budget: int) -> Program:
             ensure(d, pinned)
             pinned.add(d)
         for op in ops:
-            out.append(rename(op, {}))
+            if op.kind == "jamp" and jmem:
+                held = set()
+                for k, c in op.prm["jam"]:
+                    q = f"Q{k}"
+                    if q in cache:
+                        out.append(Op("jadd", None, [cache[q], op.ins[0]], {"k": k, "c": c}))
+                    else:
+                        nm = f"Q{k}_{version.get(q, 0)}"
+                        version[q] = version.get(q, 0) + 1
+                        out.append(Op("jset", nm, [op.ins[0]], {"k": k, "c": c}))
+                        cache[q] = nm
+                    held.add(q)
+                    evict(held)
+                out.append(Op("jsync", None, [], {}))
+            else:
+                out.append(rename(op, {}))
         evict(set())
+        item_end.append(len(out))
+    if jmem:
+        for q in sorted((v for v in cache if v.startswith("Q")), key=lambda v: int(v[1:])):
+            out.append(Op("jflush", None, [cache[q]], {"k": int(q[1:])}))
     # prog.items keeps the builder's order so that every schedule starts from
     # the same point; the chosen order is kept separately
     prog.order = order
+    prog.item_end = item_end
     prog.ops = out
     return prog
+
+
+def schedule_parts(prog: Program, budget: int, nparts: int, iters: int = 4) -> list:
+    """Kernel splitting for workspace-backed jamps: schedule the whole
+    program, cut the chosen amplitude order into ``nparts`` contiguous runs
+    of about equal executed cost, and schedule each run on its own (fresh
+    register cache; every part writes its jamp contributions back).  Returns
+    one op list per part and leaves their concatenation in prog.ops."""
+    assert getattr(prog, "jamps_in_memory", False)
+    schedule(prog, budget, iters)
+    if nparts <= 1:
+        prog.parts = [prog.ops]
+        return prog.parts
+    order = list(prog.order)
+    _schedule_once_in_order(prog, budget, order)
+    prog.order = order
+    cost, prev = [], 0
+    for end in prog.item_end:
+        cost.append(prog.flops_of(prog.ops[prev:end]))
+        prev = end
+    total = sum(cost)
+    cuts, acc, j = [], 0, 1
+    for i, c in enumerate(cost):
+        acc += c
+        if j < nparts and acc >= total * j / nparts:
+            cuts.append(i + 1)
+            j += 1
+    bounds = [0] + cuts + [len(prog.order)]
+    items = prog.items
+    parts = []
+    for a, b in zip(bounds[:-1], bounds[1:]):
+        sub = [items[i] for i in order[a:b]]
+        prog.items = sub
+        schedule(prog, budget, iters)
+        parts.append(prog.ops)
+        prog.items = items
+    prog.parts = parts
+    prog.order = order
+    prog.ops = [op for part in parts for op in part]
+    return parts
+
+
+def _schedule_once_in_order(prog: Program, budget: int, order) -> None:
+    """_schedule_once with the amplitude order fixed (used to measure the
+    cost of each amplitude in a given order)."""
+    items = prog.items
+    prog.items = [items[i] for i in order]
+    saved = _pick[0]
+    _pick[0] = lambda remaining, key: min(remaining)
+    try:
+        _schedule_once(prog, budget)
+    finally:
+        _pick[0] = saved
+        prog.items = items
+
+
+# item selection rule of _schedule_once (replaceable to fix the order)
+_pick = [lambda remaining, key: min(remaining, key=key)]
+# write-back cost of a jamp accumulator in flop equivalents (memory round trip)
+JFLUSH_COST = 48
 
 
 def peak_live(prog: Program) -> int:
@@ -582,16 +700,43 @@ def all_programs(budget=None):
     """Programs with one register schedule per arithmetic type.  Budgets are
     in FP64 dwords; an FP32 value takes half the registers, so the FP32
     schedule gets the same register count as twice the FP64 budget."""
-    progs = [eemumu_program()] + [qcd_program(ng) for ng in (2, 3, 4, 5)]
+    progs = [eemumu_program()] + [qcd_program(ng, share_half=SHARE_HALF.get(n, True))
+                                  for ng, n in ((2, "ggtt"), (3, "ggttg"), (4, "ggttgg"), (5, "ggttggg"))]
     for p in progs:
-        b64 = budget if budget is not None else DEFAULT_BUDGET_F64.get(p.name, 256)
-        b32 = budget if budget is not None else DEFAULT_BUDGET_F32.get(p.name, 512)
-        schedule(p, b32)
+        if p.name in SPLIT:
+            split_program(p, SPLIT[p.name], budget)
+            continue
+        b64, i64 = DEFAULT_SCHEDULE_F64.get(p.name, (256, 4))
+        b32, i32 = DEFAULT_SCHEDULE_F32.get(p.name, (512, 4))
+        schedule(p, budget if budget is not None else b32, i32)
         p.ops_f32 = p.ops
-        schedule(p, b64)
+        schedule(p, budget if budget is not None else b64, i64)
         p.ops_f64 = p.ops
     return progs
 
 
-DEFAULT_BUDGET_F64 = {"eemumu": 256, "ggtt": 256, "ggttg": 320, "ggttgg": 320, "ggttggg": 320}
-DEFAULT_BUDGET_F32 = {"eemumu": 256, "ggtt": 256, "ggttg": 384, "ggttgg": 384, "ggttggg": 384}
+# (budget in FP64 dwords, greedy passes) per process and arithmetic type,
+# and whether amplitudes share half contractions; chosen by measurement on
+# gfx950 (2^20 gg -> t tbar gg events)
+DEFAULT_SCHEDULE_F64 = {"eemumu": (256, 4), "ggtt": (256, 4), "ggttg": (256, 4), "ggttgg": (256, 4)}
+DEFAULT_SCHEDULE_F32 = {"eemumu": (256, 4), "ggtt": (256, 4), "ggttg": (384, 1), "ggttgg": (384, 1)}
+SHARE_HALF = {"ggttg": False, "ggttgg": False, "ggttggg": True}
+
+# Split form (jamps in a workspace, amplitudes in several kernels) for the
+# processes whose colour flows do not fit in registers: per arithmetic type
+# the wavefunction budget (FP64 dwords), the number of jamp accumulators a
+# lane holds at once and the number of parts.
+SPLIT = {"ggttggg": {"f64": (256, 16, 24), "f32": (320, 48, 12)}}
+
+
+def split_program(p: Program, cfg: dict, budget=None) -> Program:
+    p.split = True
+    p.jamps_in_memory = True
+    for tag in ("f32", "f64"):
+        b, jcap, nparts = cfg[tag]
+        p.jamp_capacity = jcap
+        parts = schedule_parts(p, budget if budget is not None else b, nparts, iters=2)
+        setattr(p, f"parts_{tag}", parts)
+    p.ops_f64 = [op for part in p.parts_f64 for op in part]
+    p.ops_f32 = [op for part in p.parts_f32 for op in part]
+    return p

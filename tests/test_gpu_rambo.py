@@ -25,7 +25,26 @@ def test_device_rambo_matches_oracle(oracle_lib, name, masses, sqs, n):
     got = d.cpu().numpy()
     ref = oracle_lib.rambo(n, masses, sqs, 77)
     rel = np.abs(got - ref).max(axis=(1, 2)) / sqs
-    assert np.median(rel) <= 1e-15 and rel.max() <= 1e-12
+    # RAMBO boosts the massless system of mass M and energy Q0 to rest: the
+    # rounding of both sides is amplified by about gamma^2, gamma = Q0 / M,
+    # which is large when the random directions nearly coincide.  gamma
+    # comes from the shared Philox uniforms.
+    u = oracle_lib.uniforms(n, len(masses), 77)
+    c = 2.0 * u[..., 0] - 1.0
+    phi = 2.0 * np.pi * u[..., 1]
+    q0 = -np.log((1.0 - u[..., 2]) * (1.0 - u[..., 3]))
+    st = np.sqrt(np.maximum(0.0, 1.0 - c * c))
+    nh = np.stack([st * np.cos(phi), st * np.sin(phi), c], axis=-1)
+    m2 = np.zeros(n)
+    for i in range(len(masses)):
+        for j in range(i + 1, len(masses)):
+            m2 += q0[:, i] * q0[:, j] * ((nh[:, i] - nh[:, j]) ** 2).sum(axis=1)
+    gamma = q0.sum(axis=1) / np.sqrt(m2)
+    tol = np.maximum(1e-12, 64 * np.finfo(np.float64).eps * gamma ** 2)
+    worst = int(np.argmax(rel / tol))
+    print(f"[rambo] worst rel {rel[worst]:.2e} at gamma {gamma[worst]:.1f} (tol {tol[worst]:.2e})")
+    assert np.median(rel) <= 1e-15
+    assert (rel <= tol).all()
     bal = got[:, 0] + got[:, 1] - got[:, 2:].sum(axis=1)
     assert np.abs(bal).max() <= 1e-11 * sqs
 

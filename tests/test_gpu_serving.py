@@ -10,7 +10,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-NAMES = ["eemumu", "ggtt", "ggttg", "ggttgg"]
+NAMES = ["eemumu", "ggtt", "ggttg", "ggttgg", "ggttggg"]
 
 
 @pytest.fixture(scope="module")
