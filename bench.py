@@ -7,8 +7,10 @@ all vertex calls of the 123 diagrams per good helicity, jamps, colour sum and
 helicity sum in one kernel.  The FP64 and mixed forms run on the same batch;
 the headline value is the mixed form's throughput, valid because its median
 relative error against the FP64 result of the same events is measured in the
-same run (target <= 1e-5).  A short Poisson serving stream adds p50/p99
-latency.  The CPU oracle is timed on a bounded sample of the same events.
+same run (target <= 1e-5).  gg > t t~ g g g (split form) is reported beside
+it at 2^20 events, FP64 and mixed.  A Poisson serving stream over all five
+processes adds p50/p99 latency.  The CPU oracle is timed on a bounded sample
+of the same events.
 
 Prints ONE JSON line.  --gpus N > 1 is refused (one GPU only).
 """
@@ -68,6 +70,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=400)
+    ap.add_argument("--ggttggg-nevt", type=int, default=1 << 20)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
@@ -87,12 +90,27 @@ def main():
     out32 = torch.empty(args.nevt, dtype=torch.float64, device=dev)
 
     me64 = MatrixElement("ggttgg", precision="fp64")
-    me32 = MatrixElement("ggttgg", precision="mixed")
-    info = me32.info
+    # the mixed form with its colour sum on FP16 hi+lo MFMA and on the vector
+    # ALU: both are timed, the faster one is the headline
+    me_mfma = MatrixElement("ggttgg", precision="mixed")
+    me_valu = MatrixElement("ggttgg", precision="mixed_valu")
+    info = me_mfma.info
     flops_evt = info["flops_per_event"]
 
     wall64, k64 = time_kernel(me64, m, out64, args.steps, args.warmup)
-    wall32, k32 = time_kernel(me32, m, out32, args.steps, args.warmup)
+    out_v = torch.empty(args.nevt, dtype=torch.float64, device=dev)
+    wall_m, k_m = time_kernel(me_mfma, m, out32, args.steps, args.warmup)
+    wall_v, k_v = time_kernel(me_valu, m, out_v, args.steps, args.warmup)
+    variants = {"mfma_f16_hilo": {"ME_s": args.nevt * args.steps / wall_m, "kernel_ms": k_m / args.steps * 1e3,
+                                  "kernel": "me_kernel_mfma<Proc_ggttgg, false>"},
+                "valu": {"ME_s": args.nevt * args.steps / wall_v, "kernel_ms": k_v / args.steps * 1e3,
+                         "kernel": "me_kernel<Proc_ggttgg, float>"}}
+    best = "valu" if wall_v < wall_m else "mfma_f16_hilo"
+    if best == "valu":
+        wall32, k32, me32 = wall_v, k_v, me_valu
+        out32 = out_v
+    else:
+        wall32, k32, me32 = wall_m, k_m, me_mfma
     r64, r32 = out64.cpu().numpy(), out32.cpu().numpy()
     rel = np.abs(r32 / r64 - 1.0)
 
@@ -119,20 +137,54 @@ def main():
         "config": {"workload": "g g > t t~ g g, 2^20 RAMBO events at sqrt(s)=1500 GeV (seed 4), "
                                "mt=173 Gt=1.49 alpha_s=0.118, zero-width t-channel mode",
                    "nevt": n, "precision": "mixed: FP32 vertices, FP64 momenta/denominators/helicity sum",
+                   "colour_sum": best,
                    "good_helicities": info["nhel_good"], "diagrams": info["ndiagrams"],
                    "colour_flows": info["ncolor"]},
         "fp64": {"value": fp64_value, "unit": "ME/s", "ms_per_step": wall64 / K * 1e3, "dtype": "f64"},
+        "mixed_variants": variants,
         "mixed_vs_fp64_speedup": value / fp64_value,
         "mixed_rel_err_vs_fp64": {"median": float(np.median(rel)), "p99": float(np.quantile(rel, 0.99)),
                                   "max": float(rel.max()), "events": n},
         "roofline": {"bound": "alu", "achieved": ach32 / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
                      "unit": "TFLOP/s", "frac": ach32 / FP32_VECTOR_PEAK, "traffic": None,
-                     "kernel": "me_kernel<Proc_ggttgg, float>",
+                     "kernel": variants[best]["kernel"],
                      "flops_per_event": flops_evt, "kernel_ms": t_launch32 * 1e3},
         "roofline_fp64": {"bound": "alu", "achieved": ach64 / 1e12, "peak": FP64_VECTOR_PEAK / 1e12,
                           "unit": "TFLOP/s", "frac": ach64 / FP64_VECTOR_PEAK,
                           "kernel": "me_kernel<Proc_ggttgg, double>", "kernel_ms": t_launch64 * 1e3},
     }
+
+    # gg -> t tbar ggg (1240 diagrams, 120 colour flows), split form: part
+    # kernels write jamps to an HBM workspace, MFMA colour-sum kernel; one
+    # step per form over 2^20 events of its own configuration (seed 5)
+    if args.ggttggg_nevt > 0:
+        n5 = args.ggttggg_nevt
+        m5 = torch.from_numpy(config_events("ggttggg", n5)).to(dev)
+        o5 = torch.empty(n5, dtype=torch.float64, device=dev)
+        rows = {}
+        res5 = {}
+        for prec in ("fp64", "mixed"):
+            me5 = MatrixElement("ggttggg", precision=prec)
+            me5(m5[:4096], o5[:4096])
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            me5(m5, o5)
+            b.record()
+            torch.cuda.synchronize()
+            t5 = a.elapsed_time(b) * 1e-3
+            f5 = me5.info["flops_per_event"]
+            peak = FP64_VECTOR_PEAK if prec == "fp64" else FP32_VECTOR_PEAK
+            rows[prec] = {"value": n5 / t5, "unit": "ME/s", "ms": t5 * 1e3,
+                          "achieved_tflops": f5 * n5 / t5 / 1e12, "peak_tflops": peak / 1e12,
+                          "frac": f5 * n5 / t5 / peak}
+            res5[prec] = o5.cpu().numpy()
+            me5.close()
+        e5 = np.abs(res5["mixed"] / res5["fp64"] - 1.0)
+        rows["mixed_rel_err_vs_fp64"] = {"median": float(np.median(e5)), "max": float(e5.max())}
+        rows["nevt"] = n5
+        rec["ggttggg"] = rows
+        del m5, o5
 
     # HBM-bound neighbours of the path: device phase-space generation and the
     # batch-unweighting reduction, timed with events on the current stream
@@ -187,16 +239,30 @@ def main():
 
     if not args.no_serving:
         from paper_2312_02898_amd.serving import make_stream, run_stream
-        names = ["eemumu", "ggtt", "ggttg", "ggttgg"]
+        names = ["eemumu", "ggtt", "ggttg", "ggttgg", "ggttggg"]
         handles = {}
+        cap = {}
         for nm in names:
             prm = B.me_default_params(precision=B.ME_MIXED)
             h = B.me_create(PROCESS_NAMES[nm], prm)
             B.me_helicity_filter(h)
             handles[nm] = h
-        # offered load ~0.7 of the measured capacity for the mean request
+            # standalone mixed throughput of this process on a 65536-event batch
+            mc = torch.from_numpy(config_events(nm, 65536)).to(dev)
+            oc = torch.empty(65536, dtype=torch.float64, device=dev)
+            B.me_compute(h, mc.data_ptr(), 65536, oc.data_ptr(), stream)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            B.me_compute(h, mc.data_ptr(), 65536, oc.data_ptr(), stream)
+            b.record()
+            torch.cuda.synchronize()
+            cap[nm] = 65536 / (a.elapsed_time(b) * 1e-3)
+        # processes drawn uniformly, sizes log-uniform in [256, 65536]:
+        # offered load 0.7 of the capacity measured above
         mean_events = (65536 - 256) / np.log(65536 / 256)
-        rate = 0.7 * value / mean_events * 1.0
+        sec_per_request = mean_events * np.mean([1.0 / cap[nm] for nm in names])
+        rate = 0.7 / sec_per_request
         arr, procs, moms = make_stream(names, args.serving_requests, rate)
         lat, status, outs, wall, st = run_stream(handles, arr, procs, moms)
         ev = sum(x.shape[0] for x in moms)
@@ -204,12 +270,14 @@ def main():
                           "p99_latency_ms": float(np.quantile(lat, 0.99) * 1e3),
                           "throughput_ME_s": ev / wall, "failed": int((status != 0).sum()),
                           "processes": names, "offered_rate_hz": rate,
+                          "standalone_mixed_ME_s": cap,
                           "peak_bytes_in_use": st["peak_bytes_in_use"]}
         for h in handles.values():
             B.me_destroy(h)
 
     me64.close()
-    me32.close()
+    me_mfma.close()
+    me_valu.close()
     print(json.dumps(rec))
 
 

@@ -48,12 +48,15 @@ struct RamboArgs {
   uint32_t k0, k1;
 };
 
+// N = number of final-state particles (a compile-time constant, so the
+// per-particle arrays live in registers)
+template <int N>
 __global__ __launch_bounds__(256) void rambo_kernel(int64_t nevt, RamboArgs a, double* __restrict__ out) {
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= nevt) return;
-  const int n = a.nfinal;
+  constexpr int n = N;
   const double pi = 3.14159265358979323846;
-  double q0[kMaxFinal], nh[kMaxFinal][3];
+  double q0[N], nh[N][3];
   for (int i = 0; i < n; ++i) {
     const U4 r0 = philox4x32_10(U4{uint32_t(e), uint32_t(uint64_t(e) >> 32), uint32_t(2 * i), 0u}, a.k0, a.k1);
     const U4 r1 = philox4x32_10(U4{uint32_t(e), uint32_t(uint64_t(e) >> 32), uint32_t(2 * i + 1), 0u}, a.k0, a.k1);
@@ -83,7 +86,7 @@ __global__ __launch_bounds__(256) void rambo_kernel(int64_t nevt, RamboArgs a, d
   const double M = sqrt(M2);
   const double b[3] = {-Q[1] / M, -Q[2] / M, -Q[3] / M};
   const double gam = Q[0] / M, aa = 1.0 / (1.0 + gam), x = a.sqrt_s / M;
-  double p[kMaxFinal][4];
+  double p[N][4];
   for (int i = 0; i < n; ++i) {
     double qv[3];
     for (int k = 0; k < 3; ++k) qv[k] = q0[i] * nh[i][k];
@@ -152,7 +155,13 @@ extern "C" me_status me_rambo(int64_t nevt, int32_t nfinal, const double* masses
   if (nevt == 0) return ME_OK;
   const int64_t blocks = (nevt + 255) / 256;
   if (blocks > 0x7fffffffLL) return ME_EINVAL;
-  hipLaunchKernelGGL(rambo_kernel, dim3(unsigned(blocks)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), nevt,
-                     a, d_momenta);
+  const dim3 grid{unsigned(blocks)}, block{256};
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  switch (nfinal) {
+    case 2: hipLaunchKernelGGL(rambo_kernel<2>, grid, block, 0, s, nevt, a, d_momenta); break;
+    case 3: hipLaunchKernelGGL(rambo_kernel<3>, grid, block, 0, s, nevt, a, d_momenta); break;
+    case 4: hipLaunchKernelGGL(rambo_kernel<4>, grid, block, 0, s, nevt, a, d_momenta); break;
+    default: hipLaunchKernelGGL(rambo_kernel<5>, grid, block, 0, s, nevt, a, d_momenta); break;
+  }
   return hipGetLastError() == hipSuccess ? ME_OK : ME_EHIP;
 }

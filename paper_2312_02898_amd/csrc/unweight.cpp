@@ -4,11 +4,12 @@
 // the batch maximum is reduced in parallel so that only one scalar returns.
 //
 // HBM-bound: 16 bytes read per event (|M|^2 and f), 8 written when the
-// weights are kept.  One grid-stride kernel: each lane keeps a running
-// maximum, the wave reduces it with cross-lane moves, one atomic per wave on
-// the bit pattern of the (non-negative) maximum.  A one-lane fill kernel
-// clears the result first, so the pair of launches is stream-ordered and
-// safe to capture in a graph.
+// weights are kept.  One grid-stride kernel of at most 1024 blocks: each lane
+// keeps a running maximum, the wave reduces it with cross-lane moves, the
+// block through LDS, and one atomic per block lands on the bit pattern of
+// the (non-negative) maximum (a few hundred atomics on one address instead
+// of one per wave).  A one-lane fill kernel clears the result first, so the
+// pair of launches is stream-ordered and safe to capture in a graph.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -36,7 +37,13 @@ __global__ __launch_bounds__(256) void max_weight_kernel(const double* __restric
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
-  if ((threadIdx.x & 63) == 0 && m > 0.0) atomicMax(d_max_bits, static_cast<unsigned long long>(__double_as_longlong(m)));
+  __shared__ double wmax[4];
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+    if (m > 0.0) atomicMax(d_max_bits, static_cast<unsigned long long>(__double_as_longlong(m)));
+  }
 }
 
 }  // namespace
@@ -48,9 +55,9 @@ extern "C" me_status me_max_weight(const double* d_me, const double* d_factor, i
   auto* bits = reinterpret_cast<unsigned long long*>(d_max);
   hipLaunchKernelGGL(max_weight_init, dim3(1), dim3(1), 0, s, bits);
   if (nevt > 0) {
-    // enough blocks to fill 256 CUs several times over, grid-stride beyond that
+    // four blocks per CU, grid-stride beyond that
     int64_t blocks = (nevt + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
+    if (blocks > 1024) blocks = 1024;
     hipLaunchKernelGGL(max_weight_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, d_me, d_factor, nevt, d_w,
                        bits);
   }

@@ -719,14 +719,14 @@ def all_programs(budget=None):
 # and whether amplitudes share half contractions; chosen by measurement on
 # gfx950 (2^20 gg -> t tbar gg events)
 DEFAULT_SCHEDULE_F64 = {"eemumu": (256, 4), "ggtt": (256, 4), "ggttg": (256, 4), "ggttgg": (256, 4)}
-DEFAULT_SCHEDULE_F32 = {"eemumu": (256, 4), "ggtt": (256, 4), "ggttg": (384, 1), "ggttgg": (384, 1)}
+DEFAULT_SCHEDULE_F32 = {"eemumu": (256, 4), "ggtt": (256, 4), "ggttg": (384, 1), "ggttgg": (384, 2)}
 SHARE_HALF = {"ggttg": False, "ggttgg": False, "ggttggg": True}
 
 # Split form (jamps in a workspace, amplitudes in several kernels) for the
 # processes whose colour flows do not fit in registers: per arithmetic type
 # the wavefunction budget (FP64 dwords), the number of jamp accumulators a
 # lane holds at once and the number of parts.
-SPLIT = {"ggttggg": {"f64": (256, 16, 24), "f32": (320, 48, 12)}}
+SPLIT = {"ggttggg": {"f64": (288, 32, 12), "f32": (384, 64, 8)}}
 
 
 def split_program(p: Program, cfg: dict, budget=None) -> Program:
