@@ -26,6 +26,46 @@ sys.path.insert(0, ROOT)
 FP32_VECTOR_PEAK = 157.3e12   # MI355X fp32 vector (packed) FLOP/s
 FP64_VECTOR_PEAK = 78.6e12    # MI355X fp64 vector FLOP/s
 
+# HBM traffic per launch of the gg -> t t~ g g mixed kernels at 2^20 events,
+# from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs (KiB per
+# dispatch), scaled by what the same counters read for a 1 GiB device copy
+# (FETCH_SIZE 0.5 GiB, WRITE_SIZE 1 GiB: scales 2 and 1).  Valid only for
+# the kernel source they were taken on (digest below); null otherwise.
+PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
+MEASURED_TRAFFIC = {
+    "valu": {"digest": "3ac665fea4097cd5", "fetch_kib": 99182, "write_kib": 8192},
+    "mfma_f16_hilo": {"digest": "ef7044a58ed3cf52", "fetch_kib": 99158, "write_kib": 100937},
+}
+
+
+def kernel_digest(variant):
+    """Digest of the sources that make the gg -> t t~ g g mixed kernel: its
+    generated FP32 amplitude function and colour form, the kernel and device
+    headers and the compiler flags."""
+    import hashlib
+    from paper_2312_02898_amd import build as pb
+    csrc = os.path.join(ROOT, "paper_2312_02898_amd", "csrc")
+    with open(os.path.join(csrc, "gen", "ggttgg_proc.inc")) as f:
+        inc = f.read()
+    a = inc.index("static void amplitudes_f32")
+    b = inc.index("\n  }\n", a)
+    h = hashlib.sha256(inc[a:b].encode())
+    if variant == "valu":
+        a = inc.index("static T colour_sum")
+        h.update(inc[a:inc.index("\n  }\n", a)].encode())
+    for f in ("kernels.hpp", "helas.hpp", "colour_mfma.hpp", "me_types.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    h.update(" ".join(pb.FLAGS[:-4]).encode())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(variant):
+    m = MEASURED_TRAFFIC.get(variant)
+    if not m or m["digest"] != kernel_digest(variant):
+        return None
+    return (m["fetch_kib"] * PMC_FETCH_SCALE + m["write_kib"] * PMC_WRITE_SCALE) * 1024.0
+
 
 def time_kernel(me, m, out, steps, warmup):
     import torch
@@ -158,7 +198,9 @@ def main():
         "mixed_rel_err_vs_fp64": {"median": float(np.median(rel)), "p99": float(np.quantile(rel, 0.99)),
                                   "max": float(rel.max()), "events": n},
         "roofline": {"bound": "alu", "achieved": ach32 / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
-                     "unit": "TFLOP/s", "frac": ach32 / FP32_VECTOR_PEAK, "traffic": None,
+                     "unit": "TFLOP/s", "frac": ach32 / FP32_VECTOR_PEAK, "traffic": measured_traffic(best),
+                     "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "algorithmic_bytes": n * info["bytes_per_event"],
                      "kernel": variants[best]["kernel"],
                      "flops_per_event": flops_evt, "kernel_ms": t_launch32 * 1e3},
         "roofline_fp64": {"bound": "alu", "achieved": ach64 / 1e12, "peak": FP64_VECTOR_PEAK / 1e12,
