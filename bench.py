@@ -144,7 +144,7 @@ def main():
     me64 = MatrixElement("ggttgg", precision="fp64")
     # the mixed form with its colour sum on FP16 hi+lo MFMA and on the vector
     # ALU: both are timed, the faster one is the headline
-    me_mfma = MatrixElement("ggttgg", precision="mixed")
+    me_mfma = MatrixElement("ggttgg", precision="mixed_mfma16")
     me_valu = MatrixElement("ggttgg", precision="mixed_valu")
     info = me_mfma.info
     flops_evt = info["flops_per_event"]

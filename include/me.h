@@ -68,14 +68,18 @@ typedef enum {
   ME_FP64 = 0,       /* all arithmetic in FP64 */
   ME_MIXED = 1,      /* FP32 wavefunctions and vertices; FP64 momenta, p^2,
                         propagator denominators and helicity-sum accumulation;
-                        colour sum on MFMA (FP16 hi+lo jamps, exact FP16
-                        colour matrix, FP32 accumulation) for 6..32 colour
-                        flows, FP32 vector ALU otherwise */
-  ME_MIXED_VALU = 2, /* as ME_MIXED with the colour sum always on the FP32
-                        vector ALU */
-  ME_MIXED_MFMA32 = 3 /* as ME_MIXED with the colour sum on MFMA with FP32
+                        colour sum on the unit measured fastest for the
+                        process (one of the three below; gg -> t t~ g g g
+                        always uses FP16 hi+lo MFMA) */
+  ME_MIXED_VALU = 2, /* as ME_MIXED with the colour sum on the FP32 vector
+                        ALU (processes of up to 32 colour flows) */
+  ME_MIXED_MFMA32 = 3, /* as ME_MIXED with the colour sum on MFMA with FP32
                         operands (exact FP32 jamps and colour matrix, no
                         hi+lo split) for 6..32 colour flows */
+  ME_MIXED_MFMA16 = 4 /* as ME_MIXED with the colour sum on MFMA with FP16
+                        hi+lo jamps, exact FP16 colour matrix and FP32
+                        accumulation, for 6..32 colour flows and the split
+                        form */
 } me_precision;
 
 /* Standard-Model inputs.  me_default_params() fills the benchmark values

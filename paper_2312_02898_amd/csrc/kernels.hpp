@@ -141,8 +141,10 @@ __global__ __launch_bounds__(256) void me_kernel_mfma(const double* __restrict__
   if (e < nevt) out[e] = acc * (P::coupling_factor(prm) / (P::CDEN * P::IDEN));
 }
 
-// mode: ME_MODE_FP64, ME_MODE_MIXED (MFMA colour sum where it pays, i.e. for
-// 6 to 32 colour flows) or ME_MODE_MIXED_VALU (colour sum on the vector ALU).  out_hel (FP64 only) receives the
+// mode: ME_MODE_FP64; ME_MODE_MIXED (colour sum on the unit chosen for the
+// process, P::MIXED_MFMA); ME_MODE_MIXED_VALU, ME_MODE_MIXED_MFMA16 or
+// ME_MODE_MIXED_MFMA32 (vector ALU, FP16 hi+lo or FP32 MFMA; the MFMA forms
+// for 6 to 32 colour flows, the vector ALU otherwise).  out_hel (FP64 only) receives the
 // colour-summed |M_h|^2 of every listed helicity, [nevt][NHEL].
 template <class P>
 int launch(int mode, const double* mom, int64_t nevt, double* out, double* out_hel, const MeParams& prm,
@@ -162,15 +164,17 @@ int launch(int mode, const double* mom, int64_t nevt, double* out, double* out_h
       hipLaunchKernelGGL((me_kernel<P, double>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
                          out_hel, prm);
     }
-  } else if ((mode == ME_MODE_MIXED || mode == ME_MODE_MIXED_MFMA32) && P::NCOLOR >= 6 && P::NCOLOR <= 32) {
+  } else if (((mode == ME_MODE_MIXED && P::MIXED_MFMA) || mode == ME_MODE_MIXED_MFMA16 ||
+              mode == ME_MODE_MIXED_MFMA32) && P::NCOLOR >= 6 && P::NCOLOR <= 32) {
     if (out_hel || !out) return -1;
-    if (mode == ME_MODE_MIXED)
+    if (mode != ME_MODE_MIXED_MFMA32)
       hipLaunchKernelGGL((me_kernel_mfma<P, false>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
                          prm);
     else
       hipLaunchKernelGGL((me_kernel_mfma<P, true>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
                          prm);
-  } else if (mode == ME_MODE_MIXED || mode == ME_MODE_MIXED_VALU || mode == ME_MODE_MIXED_MFMA32) {
+  } else if (mode == ME_MODE_MIXED || mode == ME_MODE_MIXED_VALU || mode == ME_MODE_MIXED_MFMA32 ||
+             mode == ME_MODE_MIXED_MFMA16) {
     if (out_hel) return -1;
     hipLaunchKernelGGL((me_kernel<P, float>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
                        nullptr, prm);

@@ -297,7 +297,9 @@ int launch_split(int mode, const double* mom, int64_t nevt, double* out, double*
   if (nevt <= 0) return 0;
   if ((nevt + 255) / 256 > 0x7fffffffLL) return -1;
   if (mode == ME_MODE_FP64) return run_split<P, double>(mom, nevt, out, out_hel, prm, stream, parts64, n64);
-  if (mode != ME_MODE_MIXED && mode != ME_MODE_MIXED_VALU && mode != ME_MODE_MIXED_MFMA32) return -1;
+  if (mode != ME_MODE_MIXED && mode != ME_MODE_MIXED_VALU && mode != ME_MODE_MIXED_MFMA32 &&
+      mode != ME_MODE_MIXED_MFMA16)
+    return -1;
   if (out_hel || !out) return -1;
   return run_split<P, float>(mom, nevt, out, nullptr, prm, stream, parts32, n32);
 }

@@ -707,6 +707,7 @@ def all_programs(budget=None):
             split_program(p, SPLIT[p.name], budget)
             continue
         p.fp64_lds_jamps = p.name in FP64_LDS_JAMPS
+        p.mixed_mfma = p.name in MIXED_MFMA
         b64, i64 = DEFAULT_SCHEDULE_F64.get(p.name, (256, 4))
         b32, i32 = DEFAULT_SCHEDULE_F32.get(p.name, (512, 4))
         schedule(p, budget if budget is not None else b32, i32)
@@ -725,6 +726,9 @@ SHARE_HALF = {"ggttg": False, "ggttgg": False, "ggttggg": True}
 # FP64 forms that keep their jamps in LDS (frees 4 registers per colour flow
 # for the wavefunction schedule; gg -> t tbar gg FP64 91 -> 79 ms per 2^20)
 FP64_LDS_JAMPS = {"ggttgg"}
+# processes whose default mixed form (ME_MIXED) sums colours on FP16 hi+lo
+# MFMA; the others use the vector ALU (chosen by measurement)
+MIXED_MFMA = set()
 
 # Split form (jamps in a workspace, amplitudes in several kernels) for the
 # processes whose colour flows do not fit in registers: per arithmetic type

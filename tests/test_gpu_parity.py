@@ -95,7 +95,7 @@ def test_fp64_full_size_sampled(oracle_lib, B, dev, proc):
     _check_fp64(oracle_lib, name, mom[idx], gpu[idx], ref)
 
 
-@pytest.mark.parametrize("precision", ["mixed", "mixed_valu", "mixed_mfma32"])
+@pytest.mark.parametrize("precision", ["mixed", "mixed_valu", "mixed_mfma16", "mixed_mfma32"])
 @pytest.mark.parametrize("proc", PROCS)
 def test_mixed_precision_error(oracle_lib, B, dev, proc, precision):
     mom = config_events(proc, NCHECK[proc])
@@ -169,7 +169,7 @@ def test_abi_errors(B, dev):
     B.me_destroy(h)
 
 
-@pytest.mark.parametrize("variant,med,mx", [("mixed", 1e-6, 1e-5), ("mixed_mfma32", 1e-6, 1e-5)])
+@pytest.mark.parametrize("variant,med,mx", [("mixed_mfma16", 1e-6, 1e-5), ("mixed_mfma32", 1e-6, 1e-5)])
 @pytest.mark.parametrize("proc", ["ggttg", "ggttgg"])
 def test_mfma_colour_sum_matches_valu(B, dev, proc, variant, med, mx):
     """The MFMA colour sums (FP16 hi+lo jamps or FP32 operands, FP32
