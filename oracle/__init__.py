@@ -25,6 +25,8 @@ PROCESSES = {
     "g g > t t~ g": 2,
     "g g > t t~ g g": 3,
     "g g > t t~ g g g": 4,
+    "u u~ > t t~": 5,
+    "u~ u > t t~": 6,
 }
 
 

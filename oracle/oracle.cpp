@@ -214,11 +214,14 @@ template <class T> struct Couplings {
   }
 };
 
-int npar_of(int proc) { return proc == 0 ? 4 : (proc >= 1 && proc <= 4 ? 3 + proc : -1); }
+int npar_of(int proc) { return proc == 0 || proc == 5 || proc == 6 ? 4 : (proc >= 1 && proc <= 4 ? 3 + proc : -1); }
+// light quark-antiquark annihilation into t tbar (processes 5 and 6)
+bool is_qq(int proc) { return proc == 5 || proc == 6; }
 int ngluon_of(int proc) { return proc >= 1 && proc <= 4 ? proc + 1 : 0; }
 long factorial(int n) { long f = 1; for (int i = 2; i <= n; ++i) f *= i; return f; }
 double iden_of(int proc) {
   if (proc == 0) return 4.0;
+  if (is_qq(proc)) return 36.0;   // 2 x 2 spins, 3 x 3 colours
   int nfinal_g = ngluon_of(proc) - 2;
   return 256.0 * double(factorial(nfinal_g));
 }
@@ -251,6 +254,26 @@ template <class T> cx<T> amp_eemumu(const Couplings<T>& c, const T (*p)[4], int 
   cx<T> contr = mdot(z1, z2) - mdot(z1, qv) * mdot(z2, qv) / (c.mz * c.mz);
   cx<T> m_z = (-I * c.e) * (-I * c.e) * (-I) * den * contr;
   return m_gam + m_z;
+}
+
+// ------------------------------------------------------- q qbar -> t tbar
+// Process 5 "u u~ > t t~": legs 0 q (incoming, u), 1 qbar (incoming, vbar),
+// 2 t (outgoing, ubar), 3 tbar (outgoing, v); process 6 "u~ u > t t~" has
+// the incoming legs in the other order.  One diagram, the s-channel gluon:
+//   M = A * sum_a (t^a)_{c_qbar c_q} (t^a)_{c_t c_tbar},
+//   A = [vbar gamma^mu u] (-i g)^2 (-i g_{mu nu} / s) [ubar gamma^nu v].
+template <class T> cx<T> amp_qqtt(const Couplings<T>& c, const T (*p)[4], int hel, int iq, int iqb) {
+  int lam[4];
+  for (int i = 0; i < 4; ++i) lam[i] = ((hel >> i) & 1) ? 1 : -1;
+  Sp<T> u = spinor_u(p[iq], T(0), lam[iq]);
+  Sp<T> vb = bar(spinor_v(p[iqb], T(0), lam[iqb]));
+  Sp<T> ub = bar(spinor_u(p[2], c.mt, lam[2]));
+  Sp<T> v = spinor_v(p[3], c.mt, lam[3]);
+  T q[4];
+  for (int i = 0; i < 4; ++i) q[i] = p[0][i] + p[1][i];
+  const T s = q[0] * q[0] - q[1] * q[1] - q[2] * q[2] - q[3] * q[3];
+  const cx<T> I(0, 1);
+  return (-I * c.gs) * (-I * c.gs) * (-I / s) * mdot(sandwich(vb, u), sandwich(ub, v));
 }
 
 // ------------------------------------------------------------------- QCD
@@ -497,6 +520,25 @@ std::vector<double> colour_matrix_brute(int n) {
   return out;
 }
 
+// sum over all colours of |sum_a (t^a)_{j i} (t^a)_{k l}|^2 (the colour
+// factor of q qbar -> t tbar), by brute force
+double qq_colour_factor() {
+  static const double v = [] {
+    const SU3& s = su3();
+    double acc = 0;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        for (int k = 0; k < 3; ++k)
+          for (int l = 0; l < 3; ++l) {
+            std::complex<double> x = 0;
+            for (int a = 0; a < 8; ++a) x += s.t[a][j][i] * s.t[a][k][l];
+            acc += std::norm(x);
+          }
+    return acc;
+  }();
+  return v;
+}
+
 const std::vector<double>& colour_matrix_cached(int n) {
   static std::mutex mtx;
   static std::vector<double> cache[6];
@@ -628,6 +670,7 @@ template <class T>
 T me_hel(int proc, const Couplings<T>& c, const T (*p)[4], int hel, const std::vector<double>* C,
          std::vector<cx<T>>& A) {
   if (proc == 0) return std::norm(amp_eemumu(c, p, hel));
+  if (is_qq(proc)) return T(qq_colour_factor()) * std::norm(amp_qqtt(c, p, hel, proc == 5 ? 0 : 1, proc == 5 ? 1 : 0));
   int ng = ngluon_of(proc);
   QcdEvent<T> ev = qcd_setup(c, p, ng, hel, -1);
   partial_amps(c, ev, A.data());
@@ -647,8 +690,9 @@ void run_me(int proc, const oracle_params* prm, const double* mom, int64_t nevt,
   const int npar = npar_of(proc);
   const int nhel = 1 << npar;
   const Couplings<T> c(*prm);
-  const std::vector<double>* C = proc == 0 ? nullptr : &colour_matrix_cached(ngluon_of(proc));
-  const int nf = proc == 0 ? 1 : int(factorial(ngluon_of(proc)));
+  const bool qcd_gluons = proc >= 1 && proc <= 4;
+  const std::vector<double>* C = qcd_gluons ? &colour_matrix_cached(ngluon_of(proc)) : nullptr;
+  const int nf = qcd_gluons ? int(factorial(ngluon_of(proc))) : 1;
   const T iden = T(iden_of(proc));
 #ifdef _OPENMP
   int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
@@ -793,7 +837,9 @@ int oracle_rambo(int64_t nevt, int nfinal, const double* masses, double sqrt_s, 
 
 
 int oracle_npar(int proc) { return npar_of(proc); }
-int oracle_ncolor(int proc) { return proc == 0 ? 1 : (npar_of(proc) < 0 ? -1 : int(factorial(ngluon_of(proc)))); }
+int oracle_ncolor(int proc) {
+  return proc == 0 || is_qq(proc) ? 1 : (npar_of(proc) < 0 ? -1 : int(factorial(ngluon_of(proc))));
+}
 double oracle_iden(int proc) { return npar_of(proc) < 0 ? -1.0 : iden_of(proc); }
 
 int oracle_me(int proc, const oracle_params* p, const double* mom, int64_t nevt, double* out,
@@ -818,9 +864,10 @@ int oracle_partial_amps(int proc, const oracle_params* prm, const double* mom, i
   const Couplings<double> c(*prm);
   double p[7][4];
   load_event(mom, npar, p);
-  if (proc == 0) {
+  if (proc == 0 || is_qq(proc)) {
     if (gauge_leg >= 0) return -1;
-    std::complex<double> a = amp_eemumu(c, p, hel);
+    std::complex<double> a = proc == 0 ? amp_eemumu(c, p, hel)
+                                       : amp_qqtt(c, p, hel, proc == 5 ? 0 : 1, proc == 5 ? 1 : 0);
     out[0] = a.real(); out[1] = a.imag();
     return 0;
   }
@@ -836,7 +883,8 @@ int oracle_partial_amps(int proc, const oracle_params* prm, const double* mom, i
 int oracle_dressed_amp(int proc, const oracle_params* prm, const double* mom, int hel,
                        const int* colours, double* out) {
   const int npar = npar_of(proc);
-  if (proc < 1 || npar < 0 || !prm || !mom || !colours || !out || hel < 0 || hel >= (1 << npar)) return -1;
+  if (proc < 1 || proc > 4 || npar < 0 || !prm || !mom || !colours || !out || hel < 0 || hel >= (1 << npar))
+    return -1;
   int ng = ngluon_of(proc);
   for (int g = 0; g < ng; ++g)
     if (colours[g] < 0 || colours[g] > 7) return -1;

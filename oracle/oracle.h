@@ -24,7 +24,9 @@
  *
  * Conventions shared with callers (interface, not arithmetic):
  *   process ids: 0 "e+ e- > mu+ mu-", 1 "g g > t t~", 2 "g g > t t~ g",
- *                3 "g g > t t~ g g", 4 "g g > t t~ g g g".
+ *                3 "g g > t t~ g g", 4 "g g > t t~ g g g", 5 "u u~ > t t~",
+ *                6 "u~ u > t t~" (massless light quark; the q qbar channels
+ *                of p p > t t~ beside g g > t t~).
  *   momenta:     double mom[nevt][npar][4], (E,px,py,pz) in GeV, legs 0 and 1
  *                incoming, the others outgoing, leg order = process string.
  *   helicity index h in [0, 2^npar): leg i has helicity +1 if bit i of h is

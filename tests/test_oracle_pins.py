@@ -474,3 +474,31 @@ def test_philox_uniformity(oracle_lib):
     assert np.abs(c - np.eye(4)).max() < 0.03
     # different seeds and counters give different streams
     assert not np.array_equal(oracle_lib.uniforms(8, 2, 1), oracle_lib.uniforms(8, 2, 2))
+
+
+def test_qqbar_ttbar_closed_form(oracle_lib):
+    """q qbar -> t tbar through one s-channel gluon: spin- and colour-averaged
+    |M|^2 = (4/9) g_s^4 [(m^2 - t)^2 + (m^2 - u)^2 + 2 m^2 s] / s^2
+    (Combridge 1979; Gluck, Owens, Reya 1978).  This fixes the light-quark
+    spinors, the gluon propagator, the colour factor Tr(t^a t^b) Tr(t^a t^b) = 2
+    and the averaging 1/36.  The channel with the incoming legs swapped gives
+    the same values with swapped momenta."""
+    mom = config_events("ggtt", 400)
+    g2 = 4 * np.pi * 0.118
+    m2 = 173.0 ** 2
+
+    def mdot(a, b):
+        return a[..., 0] * b[..., 0] - (a[..., 1:] * b[..., 1:]).sum(axis=-1)
+    s = mdot(mom[:, 0] + mom[:, 1], mom[:, 0] + mom[:, 1])
+    t = mdot(mom[:, 0] - mom[:, 2], mom[:, 0] - mom[:, 2])
+    u = mdot(mom[:, 0] - mom[:, 3], mom[:, 0] - mom[:, 3])
+    ref = 4.0 / 9.0 * g2 ** 2 * ((m2 - t) ** 2 + (m2 - u) ** 2 + 2 * m2 * s) / s ** 2
+    got = oracle_lib.me("u u~ > t t~", mom)
+    assert np.abs(got / ref - 1).max() <= 1e-12
+    swapped = np.ascontiguousarray(mom[:, [1, 0, 2, 3]])
+    assert np.abs(oracle_lib.me("u~ u > t t~", swapped) / got - 1).max() <= 1e-14
+    # massless quarks: only opposite q and qbar helicities couple to the gluon
+    hel = oracle_lib.me_hel("u u~ > t t~", mom[:8])
+    for h in range(16):
+        if ((h >> 0) & 1) == ((h >> 1) & 1):
+            assert np.abs(hel[:, h]).max() <= 1e-12 * hel.sum(axis=1).max()
