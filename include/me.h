@@ -133,6 +133,31 @@ me_status me_helicity_filter(me_handle h);
 me_status me_compute(me_handle h, const double* d_momenta, int64_t nevt, double* d_me,
                      void* hip_stream);
 
+/* Multi-subprocess request: event e of the batch is evaluated with
+ * handles[d_channel[e]] (e.g. the g g, u u~ and u~ u channels of
+ * p p > t t~; the paper's Summary names p p -> t tbar + jets, whose
+ * subprocesses share the final state and the momenta layout).
+ *   handles      nchannels (1..32) handles with the same number of legs; each
+ *                keeps its own precision and helicity selection.
+ *   d_momenta    device [nevt][npar][4], as for me_compute.
+ *   d_channel    device int32 [nevt], values in [0, nchannels).
+ *   d_alphas     device [nevt] per-event strong coupling, or NULL.  Every
+ *                diagram of these processes carries the same power of g_s, so
+ *                |M|^2 = |M|^2(alpha_s of the handle) x (alpha_s(e) /
+ *                alpha_s of the handle)^p exactly, p = 2 for 2 -> t t~ and one
+ *                more per extra gluon (0 for e+ e- > mu+ mu-).
+ *   d_me         device [nevt] output, FP64.
+ * The events are partitioned by channel on the device (stable), gathered,
+ * evaluated and scattered back.  Workspace (about 32 npar + 16 bytes per
+ * event) comes from the stream-ordered allocator.  The call waits for the
+ * per-channel counts (one short synchronisation of the stream); the
+ * evaluation itself stays asynchronous.  ME_EINVAL for a channel index out of
+ * range (nothing is written), mismatched legs or null pointers; ME_ENOMEM if
+ * the workspace cannot be allocated. */
+me_status me_compute_channels(const me_handle* handles, int32_t nchannels, const double* d_momenta,
+                              const int32_t* d_channel, const double* d_alphas, int64_t nevt,
+                              double* d_me, void* hip_stream);
+
 /* Colour-summed (not averaged) |M_h|^2 of all 2^npar helicity configurations,
  * d_me_hel [nevt][2^npar], FP64.  Diagnostic; asynchronous. */
 me_status me_compute_helicities(me_handle h, const double* d_momenta, int64_t nevt,

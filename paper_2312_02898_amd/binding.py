@@ -78,7 +78,7 @@ EXPORTS = [
     "me_default_params", "me_create", "me_helicity_filter", "me_compute", "me_compute_helicities",
     "me_good_helicities", "me_info", "me_destroy", "me_last_error",
     "me_server_create", "me_server_submit", "me_server_poll", "me_server_wait", "me_server_stats",
-    "me_server_destroy", "me_max_weight", "me_rambo",
+    "me_server_destroy", "me_max_weight", "me_rambo", "me_compute_channels",
 ]
 
 _lib = None
@@ -107,6 +107,7 @@ def lib():
                 getattr(L, name).restype = i32
         L.me_max_weight.argtypes = [vp, vp, i64, vp, vp, vp]
         L.me_rambo.argtypes = [i64, i32, P(d), d, ctypes.c_uint64, vp, vp]
+        L.me_compute_channels.argtypes = [P(vp), i32, vp, vp, vp, i64, vp, vp]
         if hasattr(L, "me_server_create"):
             L.me_server_create.argtypes = [i64, i32, P(vp)]
             L.me_server_submit.argtypes = [vp, vp, vp, i64, vp, P(i64)]
@@ -180,6 +181,16 @@ def me_rambo(nevt: int, masses, sqrt_s: float, seed: int, d_momenta: int, stream
     m = (ctypes.c_double * len(masses))(*[float(x) for x in masses])
     _check(lib().me_rambo(int(nevt), len(masses), m, float(sqrt_s), int(seed), d_momenta or None, stream or None),
            "me_rambo")
+
+
+def me_compute_channels(handles, d_momenta: int, d_channel: int, d_alphas: int, nevt: int, d_out: int,
+                        stream: int = 0) -> None:
+    """Multi-subprocess batch: event e evaluated by handles[channel[e]],
+    optionally rescaled to a per-event alpha_s (device pointers; d_alphas may
+    be 0)."""
+    arr = (ctypes.c_void_p * len(handles))(*handles)
+    _check(lib().me_compute_channels(arr, len(handles), d_momenta or None, d_channel or None, d_alphas or None,
+                                     int(nevt), d_out or None, stream or None), "me_compute_channels")
 
 
 def me_last_error() -> str:

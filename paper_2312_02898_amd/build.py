@@ -23,7 +23,7 @@ GEN = os.path.join(CSRC, "gen")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libme_mi355x.so")
 
-PROCESSES = ["eemumu", "ggtt", "ggttg", "ggttgg", "ggttggg"]
+PROCESSES = ["eemumu", "ggtt", "ggttg", "ggttgg", "ggttggg", "uutt", "uxutt"]
 
 HIPCC = os.environ.get("HIPCC", "hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -67,10 +67,13 @@ def build(processes=None, jobs=None, verbose=True) -> str:
     # a part kernel of a split process, <name>__<form>_<j>.hip, shares <name>_proc.inc
     units = [(s, hdrs + [os.path.join(GEN, os.path.basename(s)[:-4].split("__")[0] + "_proc.inc")])
              for s in srcs]
-    units.append((os.path.join(CSRC, "runtime.cpp"), hdrs + [table, os.path.join(ROOT, "include", "me.h")]))
-    for extra in ("server.cpp", "unweight.cpp", "rambo.cpp"):
+    units.append((os.path.join(CSRC, "runtime.cpp"), hdrs + [table, os.path.join(ROOT, "include", "me.h"),
+                                                             os.path.join(CSRC, "channels.hpp"),
+                                                             os.path.join(CSRC, "handle.hpp")]))
+    for extra in ("server.cpp", "unweight.cpp", "rambo.cpp", "channels.cpp"):
         units.append((os.path.join(CSRC, extra),
-                      hdrs + [os.path.join(CSRC, "server_core.hpp"), os.path.join(ROOT, "include", "me.h")]))
+                      hdrs + [os.path.join(CSRC, "server_core.hpp"), os.path.join(CSRC, "channels.hpp"),
+                              os.path.join(ROOT, "include", "me.h")]))
     jobs = jobs or min(len(units), os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda u: _compile(*u), units))

@@ -1,0 +1,25 @@
+// The handle behind the C ABI (internal to the library).
+#pragma once
+#include "me.h"
+#include "me_types.h"
+
+struct me_handle_s {
+  const me::ProcessEntry* proc;
+  me_sm_params params;
+  me::MeParams kp;        // kernel parameters incl. the good-helicity list
+  int filtered;
+  int device;
+};
+
+namespace me {
+
+// kernel mode of a handle's precision
+inline int mode_of(const me_sm_params& p) {
+  return p.precision == ME_MIXED          ? ME_MODE_MIXED
+         : p.precision == ME_MIXED_VALU   ? ME_MODE_MIXED_VALU
+         : p.precision == ME_MIXED_MFMA32 ? ME_MODE_MIXED_MFMA32
+         : p.precision == ME_MIXED_MFMA16 ? ME_MODE_MIXED_MFMA16
+                                          : ME_MODE_FP64;
+}
+
+}  // namespace me

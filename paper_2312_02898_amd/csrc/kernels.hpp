@@ -68,17 +68,17 @@ struct LdsJamps {
   __device__ __forceinline__ cx<T>& operator[](int k) const { return base[k * 64]; }
 };
 
-// FP64 form with the jamps in LDS (frees 4*NCOLOR registers per lane for the
-// wavefunction schedule).  128-thread blocks: 2 waves x NCOLOR x 64 x 16 B.
-template <class P>
+// The jamps in LDS (frees 2 sizeof(T)/4 * NCOLOR registers per lane for the
+// wavefunction schedule).  128-thread blocks: 2 waves x NCOLOR x 64 complex.
+template <class P, class T>
 __global__ __launch_bounds__(128) void me_kernel_ldsjamp(const double* __restrict__ mom, int64_t nevt,
                                                           double* __restrict__ out, double* __restrict__ out_hel,
                                                           const MeParams prm) {
-  __shared__ cx<double> lds[2 * P::NCOLOR * 64];
+  __shared__ cx<T> lds[2 * P::NCOLOR * 64];
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= nevt) return;
-  LdsJamps<double> jamp{lds + wave * P::NCOLOR * 64 + lane};
+  LdsJamps<T> jamp{lds + wave * P::NCOLOR * 64 + lane};
   double p[P::NPAR][4];
   const double2* src = reinterpret_cast<const double2*>(mom + e * (4 * P::NPAR));
 #pragma unroll
@@ -93,8 +93,8 @@ __global__ __launch_bounds__(128) void me_kernel_ldsjamp(const double* __restric
 #pragma unroll
       for (int c = 0; c < 4; ++c) asm volatile("" : "+v"(p[i][c]));
     const unsigned hel = prm.hel[ih];
-    P::template amplitudes<double>(p, hel, prm, jamp);
-    const double q = P::template colour_sum<double>(jamp);
+    P::template amplitudes<T>(p, hel, prm, jamp);
+    const double q = double(P::template colour_sum<T>(jamp));
     if (out_hel) out_hel[e * P::NHEL + hel] = q * (P::coupling_factor(prm) / P::CDEN);
     acc += q;
   }
@@ -158,8 +158,8 @@ int launch(int mode, const double* mom, int64_t nevt, double* out, double* out_h
     // one FP64 kernel per process, chosen when the process is generated
     if constexpr (P::FP64_LDS_JAMPS) {
       const int64_t nb = (nevt + 127) / 128;
-      hipLaunchKernelGGL((me_kernel_ldsjamp<P>), dim3(unsigned(nb)), dim3(128), 0, stream, mom, nevt, out,
-                         out_hel, prm);
+      hipLaunchKernelGGL((me_kernel_ldsjamp<P, double>), dim3(unsigned(nb)), dim3(128), 0, stream, mom, nevt,
+                         out, out_hel, prm);
     } else {
       hipLaunchKernelGGL((me_kernel<P, double>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
                          out_hel, prm);
@@ -176,8 +176,14 @@ int launch(int mode, const double* mom, int64_t nevt, double* out, double* out_h
   } else if (mode == ME_MODE_MIXED || mode == ME_MODE_MIXED_VALU || mode == ME_MODE_MIXED_MFMA32 ||
              mode == ME_MODE_MIXED_MFMA16) {
     if (out_hel) return -1;
-    hipLaunchKernelGGL((me_kernel<P, float>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
-                       nullptr, prm);
+    if constexpr (P::F32_LDS_JAMPS) {
+      const int64_t nb = (nevt + 127) / 128;
+      hipLaunchKernelGGL((me_kernel_ldsjamp<P, float>), dim3(unsigned(nb)), dim3(128), 0, stream, mom, nevt,
+                         out, nullptr, prm);
+    } else {
+      hipLaunchKernelGGL((me_kernel<P, float>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
+                         nullptr, prm);
+    }
   } else {
     return -1;
   }

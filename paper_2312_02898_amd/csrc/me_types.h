@@ -30,6 +30,7 @@ struct ProcessEntry {
   int npar, ncolor, nhel, ndiagrams, iden, colour_den;
   long flops_per_hel;  // algorithmic flops of one helicity of one event
   int massive_top;     // legs 2 and 3 carry the top mass
+  int alphas_power;    // |M|^2 is proportional to alpha_s^alphas_power
   LaunchFn launch;
 };
 

@@ -9,6 +9,8 @@
 #include <vector>
 
 #include "me.h"
+#include "channels.hpp"
+#include "handle.hpp"
 #include "me_types.h"
 #include "gen/process_table.inc"
 
@@ -104,13 +106,6 @@ void rambo_event(SplitMix64& rng, double sqrt_s, const std::vector<double>& mass
 
 }  // namespace
 
-struct me_handle_s {
-  const me::ProcessEntry* proc;
-  me_sm_params params;
-  me::MeParams kp;        // kernel parameters incl. the good-helicity list
-  int filtered;
-  int device;
-};
 
 extern "C" {
 
@@ -221,16 +216,62 @@ me_status me_compute(me_handle h, const double* d_momenta, int64_t nevt, double*
   if (nevt < 0) return fail(ME_EINVAL, "me_compute: nevt < 0");
   if (nevt == 0) return ME_OK;
   if (!d_momenta || !d_me) return fail(ME_EINVAL, "me_compute: null pointer");
-  const int mode = h->params.precision == ME_MIXED          ? me::ME_MODE_MIXED
-                   : h->params.precision == ME_MIXED_VALU   ? me::ME_MODE_MIXED_VALU
-                   : h->params.precision == ME_MIXED_MFMA32 ? me::ME_MODE_MIXED_MFMA32
-                   : h->params.precision == ME_MIXED_MFMA16 ? me::ME_MODE_MIXED_MFMA16
-                                                            : me::ME_MODE_FP64;
-  int rc = h->proc->launch(mode, d_momenta, nevt, d_me, nullptr, &h->kp, static_cast<hipStream_t>(hip_stream));
+  int rc = h->proc->launch(me::mode_of(h->params), d_momenta, nevt, d_me, nullptr, &h->kp,
+                           static_cast<hipStream_t>(hip_stream));
   if (rc != 0) {
     hipError_t le = hipGetLastError();
     return fail(ME_EHIP, std::string("me_compute: launch failed: ") + hipGetErrorString(le));
   }
+  return ME_OK;
+}
+
+me_status me_compute_channels(const me_handle* handles, int32_t nchannels, const double* d_momenta,
+                              const int32_t* d_channel, const double* d_alphas, int64_t nevt, double* d_me,
+                              void* hip_stream) {
+  if (!handles || nchannels < 1 || nchannels > me::chan::kMaxChannels)
+    return fail(ME_EINVAL, "me_compute_channels: need 1..32 handles");
+  for (int c = 0; c < nchannels; ++c)
+    if (!handles[c]) return fail(ME_EINVAL, "me_compute_channels: null handle");
+  const int npar = handles[0]->proc->npar;
+  for (int c = 1; c < nchannels; ++c)
+    if (handles[c]->proc->npar != npar)
+      return fail(ME_EINVAL, "me_compute_channels: channels must have the same number of legs");
+  if (nevt < 0) return fail(ME_EINVAL, "me_compute_channels: nevt < 0");
+  if (nevt == 0) return ME_OK;
+  if (!d_momenta || !d_channel || !d_me) return fail(ME_EINVAL, "me_compute_channels: null pointer");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  void* base = nullptr;
+  if (hipMallocAsync(&base, me::chan::workspace_bytes(nevt, nchannels, npar), s) != hipSuccess)
+    return fail(ME_ENOMEM, "me_compute_channels: no device memory for the workspace");
+  const me::chan::Workspace w = me::chan::carve(base, nevt, nchannels, npar);
+  int64_t totals[me::chan::kMaxChannels];
+  int32_t bad = 0;
+  hipError_t err = me::chan::partition(d_channel, nevt, nchannels, w, totals, &bad, s);
+  if (err != hipSuccess || bad) {
+    (void)hipFreeAsync(base, s);
+    if (err != hipSuccess) return hip_fail(err, "me_compute_channels: partition");
+    return fail(ME_EINVAL, "me_compute_channels: channel index out of range");
+  }
+  me::chan::Scale sc;
+  int64_t off = 0;
+  for (int c = 0; c < nchannels; ++c) {
+    sc.aref[c] = handles[c]->params.alpha_s;
+    sc.power[c] = handles[c]->proc->alphas_power;
+    if (totals[c] == 0) continue;
+    err = me::chan::gather(d_momenta, w.perm + off, totals[c], npar, w.mom + off * 4 * npar, s);
+    if (err != hipSuccess) break;
+    const me_handle h = handles[c];
+    if (h->proc->launch(me::mode_of(h->params), w.mom + off * 4 * npar, totals[c], w.out + off, nullptr, &h->kp,
+                        s) != 0) {
+      err = hipGetLastError();
+      if (err == hipSuccess) err = hipErrorLaunchFailure;
+      break;
+    }
+    off += totals[c];
+  }
+  if (err == hipSuccess) err = me::chan::scatter(w.out, w.perm, d_channel, d_alphas, sc, nevt, d_me, s);
+  (void)hipFreeAsync(base, s);
+  if (err != hipSuccess) return hip_fail(err, "me_compute_channels");
   return ME_OK;
 }
 

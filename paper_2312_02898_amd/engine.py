@@ -13,7 +13,34 @@ PROCESS_NAMES = {
     "ggttg": "g g > t t~ g",
     "ggttgg": "g g > t t~ g g",
     "ggttggg": "g g > t t~ g g g",
+    "uutt": "u u~ > t t~",
+    "uxutt": "u~ u > t t~",
 }
+
+
+class ChannelMix:
+    """Several subprocesses of one final state behind one call: event e is
+    evaluated by channel[e] (an index into `processes`), optionally at its own
+    alpha_s."""
+
+    def __init__(self, processes, precision: str = "fp64", filter_helicities: bool = True, **params):
+        self.members = [MatrixElement(p, precision, filter_helicities, **params) for p in processes]
+
+    def __call__(self, momenta: torch.Tensor, channel: torch.Tensor, alphas: torch.Tensor | None = None,
+                 out: torch.Tensor | None = None) -> torch.Tensor:
+        n = momenta.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=momenta.device)
+        ch = channel.to(dtype=torch.int32).contiguous()
+        a = alphas.to(dtype=torch.float64).contiguous() if alphas is not None else None
+        B.me_compute_channels([m.handle for m in self.members], momenta.data_ptr(), ch.data_ptr(),
+                              a.data_ptr() if a is not None else 0, n, out.data_ptr(),
+                              torch.cuda.current_stream().cuda_stream)
+        return out
+
+    def close(self):
+        for m in self.members:
+            m.close()
 
 
 class MatrixElement:

@@ -30,6 +30,8 @@ PROCESS_LEGS = {
     "g g > t t~ g": (0.0, 0.0, 173.0, 173.0, 0.0),
     "g g > t t~ g g": (0.0, 0.0, 173.0, 173.0, 0.0, 0.0),
     "g g > t t~ g g g": (0.0, 0.0, 173.0, 173.0, 0.0, 0.0, 0.0),
+    "u u~ > t t~": (0.0, 0.0, 173.0, 173.0),
+    "u~ u > t t~": (0.0, 0.0, 173.0, 173.0),
 }
 
 
@@ -138,6 +140,9 @@ CONFIGS = {
     "ggttg": ("g g > t t~ g", 1500.0, 1 << 20, 3),
     "ggttgg": ("g g > t t~ g g", 1500.0, 1 << 20, 4),
     "ggttggg": ("g g > t t~ g g g", 1500.0, 1 << 20, 5),
+    # light-quark channels of p p > t t~ (same kinematics as g g > t t~)
+    "uutt": ("u u~ > t t~", 1500.0, 1 << 19, 6),
+    "uxutt": ("u~ u > t t~", 1500.0, 1 << 19, 7),
 }
 
 

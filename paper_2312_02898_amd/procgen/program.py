@@ -445,6 +445,36 @@ def eemumu_program() -> Program:
     return prog
 
 
+# ------------------------------------------------------- q qbar -> t tbar
+def qqtt_program(quark_first: bool = True) -> Program:
+    """u u~ > t t~ (quark_first) or u~ u > t t~: the light-quark channels of
+    p p > t t~.  One diagram, the s-channel gluon between the light line and
+    the top line.  Its colour structure (t^a)_{c_qbar c_q} (t^a)_{c_t c_tbar}
+    is the single colour flow; summed over colours it gives
+    Tr(t^a t^b) Tr(t^a t^b) = 2, the 1x1 colour matrix."""
+    name, proc = ("uutt", "u u~ > t t~") if quark_first else ("uxutt", "u~ u > t t~")
+    q, qb = (0, 1) if quark_first else (1, 0)
+    prog = Program(name=name, process=proc, npar=4, leg_sign=[1, 1, -1, -1],
+                   ncolor=1, colour_num=[[2]], colour_den=1, iden=36, n_diagrams=1)
+    m = 0b0011
+    prog.dens[m] = "gluon"
+
+    def define(nm, ops):
+        ops = [add_kinematics(prog, op) for op in ops]
+        prog.values[nm] = ops
+        prog.deps[nm] = [v for op in ops for v in op.ins if v != nm]
+
+    define(f"w{q}", [Op("ext_u", f"w{q}", [], {"leg": q})])          # incoming quark
+    define(f"w{qb}", [Op("ext_vbar", f"w{qb}", [], {"leg": qb})])    # incoming antiquark
+    define("wT", [Op("ext_ubar", "wT", [], {"leg": 2})])
+    define("wTB", [Op("ext_v", "wTB", [], {"leg": 3})])
+    define("JQ", [Op("ffv_v0", "JQ", [f"w{qb}", f"w{q}"], {"m": m})])
+    ops = [Op("amp_ffv", "a0", ["wT", "JQ", "wTB"], {}),
+           Op("jamp", None, ["a0"], {"jam": [(0, 1 + 0j)]})]
+    prog.items.append((ops, ["wT", "JQ", "wTB"]))
+    return prog
+
+
 # --------------------------------------------------------------- scheduling
 def _closure(prog, names):
     seen = []
@@ -702,6 +732,7 @@ def all_programs(budget=None):
     schedule gets the same register count as twice the FP64 budget."""
     progs = [eemumu_program()] + [qcd_program(ng, share_half=SHARE_HALF.get(n, True))
                                   for ng, n in ((2, "ggtt"), (3, "ggttg"), (4, "ggttgg"), (5, "ggttggg"))]
+    progs += [qqtt_program(True), qqtt_program(False)]
     for p in progs:
         if p.name in SPLIT:
             split_program(p, SPLIT[p.name], budget)

@@ -19,9 +19,10 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-PROCS = ["eemumu", "ggtt", "ggttg", "ggttgg"]
+PROCS = ["eemumu", "ggtt", "ggttg", "ggttgg", "uutt", "uxutt"]
 # events checked element-wise against the oracle (all of ee->mumu's batch)
-NCHECK = {"eemumu": 16384, "ggtt": 4096 + 37, "ggttg": 2048 + 37, "ggttgg": 1024 + 37}
+NCHECK = {"eemumu": 16384, "ggtt": 4096 + 37, "ggttg": 2048 + 37, "ggttgg": 1024 + 37, "uutt": 4096 + 37,
+          "uxutt": 4096 + 37}
 
 
 @pytest.fixture(scope="module")
