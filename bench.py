@@ -111,6 +111,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=400)
     ap.add_argument("--ggttggg-nevt", type=int, default=1 << 20)
+    ap.add_argument("--channels-nevt", type=int, default=1 << 20)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
@@ -239,6 +240,31 @@ def main():
         rows["nevt"] = n5
         rec["ggttggg"] = rows
         del m5, o5
+
+    # p p > t t~ as one multi-subprocess batch: channels g g, u u~, u~ u drawn
+    # per event, each event at its own alpha_s (me_compute_channels)
+    if args.channels_nevt > 0:
+        from paper_2312_02898_amd.engine import ChannelMix
+        nc = args.channels_nevt
+        rng = np.random.default_rng(8)
+        mc = torch.from_numpy(config_events("ggtt", nc)).to(dev)
+        chn = torch.from_numpy(rng.integers(0, 3, size=nc).astype(np.int32)).to(dev)
+        als = torch.from_numpy(rng.uniform(0.10, 0.13, size=nc)).to(dev)
+        oc = torch.empty(nc, dtype=torch.float64, device=dev)
+        crow = {"nevt": nc, "channels": ["g g > t t~", "u u~ > t t~", "u~ u > t t~"]}
+        for prec in ("fp64", "mixed"):
+            mix = ChannelMix(["ggtt", "uutt", "uxutt"], prec)
+            mix(mc, chn, als, oc)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                mix(mc, chn, als, oc)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / 5
+            crow[prec] = {"value": nc / dt, "unit": "ME/s", "ms": dt * 1e3}
+            mix.close()
+        rec["pp_ttbar_channels"] = crow
+        del mc, chn, als, oc
 
     # HBM-bound neighbours of the path: device phase-space generation and the
     # batch-unweighting reduction, timed with events on the current stream
