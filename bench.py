@@ -378,19 +378,43 @@ def main():
             torch.cuda.synchronize()
             cap[nm] = 65536 / (a.elapsed_time(b) * 1e-3)
         # processes drawn uniformly, sizes log-uniform in [256, 65536]:
-        # offered load 0.7 of the capacity measured above
+        # offered loads 0.5, 0.7, 0.9 of the capacity measured above, and a
+        # small arena (64 MiB) at 0.7 so that admission by memory engages
         mean_events = (65536 - 256) / np.log(65536 / 256)
         sec_per_request = mean_events * np.mean([1.0 / cap[nm] for nm in names])
-        rate = 0.7 / sec_per_request
-        arr, procs, moms = make_stream(names, args.serving_requests, rate)
-        lat, status, outs, wall, st = run_stream(handles, arr, procs, moms)
-        ev = sum(x.shape[0] for x in moms)
-        rec["serving"] = {"requests": len(moms), "p50_latency_ms": float(np.median(lat) * 1e3),
-                          "p99_latency_ms": float(np.quantile(lat, 0.99) * 1e3),
-                          "throughput_ME_s": ev / wall, "failed": int((status != 0).sum()),
-                          "processes": names, "offered_rate_hz": rate,
-                          "standalone_mixed_ME_s": cap,
-                          "peak_bytes_in_use": st["peak_bytes_in_use"]}
+
+        # one stream of requests; exponential gaps scale with 1/rate, so each
+        # load replays the same requests with rescaled arrival times
+        arr1, procs, moms = make_stream(names, args.serving_requests, 1.0)
+
+        def serve(load, budget):
+            rate = load / sec_per_request
+            arr = arr1 / rate
+            qs = []
+            lat, status, outs, wall, st = run_stream(handles, arr, procs, moms, budget_bytes=budget, times=qs)
+            ev = sum(x.shape[0] for x in moms)
+            q = np.array([t[0] for t in qs])
+            sv = np.array([t[1] for t in qs])
+            per = {}
+            for nm in names:
+                idx = [k for k, p_ in enumerate(procs) if p_ == nm]
+                if idx:
+                    per[nm] = {"requests": len(idx), "p50_latency_ms": float(np.median(lat[idx]) * 1e3),
+                               "p99_latency_ms": float(np.quantile(lat[idx], 0.99) * 1e3)}
+            return {"offered_load": load, "offered_rate_hz": rate, "budget_bytes": budget,
+                    "requests": len(moms), "p50_latency_ms": float(np.median(lat) * 1e3),
+                    "p99_latency_ms": float(np.quantile(lat, 0.99) * 1e3),
+                    "queue_ms": {"p50": float(np.median(q) * 1e3), "p99": float(np.quantile(q, 0.99) * 1e3)},
+                    "service_ms": {"p50": float(np.median(sv) * 1e3), "p99": float(np.quantile(sv, 0.99) * 1e3)},
+                    "throughput_ME_s": ev / wall, "failed": int((status != 0).sum()),
+                    "peak_bytes_in_use": st["peak_bytes_in_use"], "per_process": per}
+
+        runs = [serve(0.7, 4 << 30), serve(0.5, 4 << 30), serve(0.9, 4 << 30), serve(0.7, 64 << 20)]
+        head = runs[0]
+        rec["serving"] = {"requests": head["requests"], "p50_latency_ms": head["p50_latency_ms"],
+                          "p99_latency_ms": head["p99_latency_ms"], "throughput_ME_s": head["throughput_ME_s"],
+                          "failed": sum(r["failed"] for r in runs), "processes": names,
+                          "standalone_mixed_ME_s": cap, "runs": runs}
         for h in handles.values():
             B.me_destroy(h)
 

@@ -234,6 +234,11 @@ me_status me_server_poll(me_server s, int64_t ticket, int32_t* done, me_status* 
 me_status me_server_wait(me_server s, int64_t ticket, double timeout_s, me_status* result,
                          double* latency_s);
 
+/* For a finished ticket: time from submit to admission (slot and arena
+ * memory granted, queueing) and from admission to completion (service:
+ * staging copies, kernels, copy back).  ME_EBUSY while it runs. */
+me_status me_server_times(me_server s, int64_t ticket, double* queue_s, double* service_s);
+
 me_status me_server_stats(me_server s, me_server_stats_t* st);
 
 /* Drain in-flight work, stop the loop and free all resources. */

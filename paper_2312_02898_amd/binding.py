@@ -78,7 +78,7 @@ EXPORTS = [
     "me_default_params", "me_create", "me_helicity_filter", "me_compute", "me_compute_helicities",
     "me_good_helicities", "me_info", "me_destroy", "me_last_error",
     "me_server_create", "me_server_submit", "me_server_poll", "me_server_wait", "me_server_stats",
-    "me_server_destroy", "me_max_weight", "me_rambo", "me_compute_channels",
+    "me_server_destroy", "me_max_weight", "me_rambo", "me_compute_channels", "me_server_times",
 ]
 
 _lib = None
@@ -114,6 +114,7 @@ def lib():
             L.me_server_poll.argtypes = [vp, i64, P(i32), P(i32), P(d)]
             L.me_server_wait.argtypes = [vp, i64, d, P(i32), P(d)]
             L.me_server_stats.argtypes = [vp, P(me_server_stats_t)]
+            L.me_server_times.argtypes = [vp, i64, P(d), P(d)]
             L.me_server_destroy.argtypes = [vp]
         _lib = L
     return _lib
@@ -229,6 +230,13 @@ def me_server_wait(server: int, ticket: int, timeout_s: float = 60.0):
     st = lib().me_server_wait(server, ticket, float(timeout_s), ctypes.byref(res), ctypes.byref(lat))
     _check(st, "me_server_wait")
     return res.value, lat.value
+
+
+def me_server_times(server: int, ticket: int):
+    """(queue_s, service_s) of a finished ticket."""
+    q, sv = ctypes.c_double(), ctypes.c_double()
+    _check(lib().me_server_times(server, ticket, ctypes.byref(q), ctypes.byref(sv)), "me_server_times")
+    return q.value, sv.value
 
 
 def me_server_stats(server: int) -> dict:

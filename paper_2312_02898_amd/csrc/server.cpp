@@ -133,6 +133,16 @@ me_status me_server_wait(me_server s, int64_t ticket, double timeout_s, me_statu
   return ME_OK;
 }
 
+me_status me_server_times(me_server s, int64_t ticket, double* queue_s, double* service_s) {
+  if (!s || !queue_s || !service_s) return ME_EINVAL;
+  me::TicketState t;
+  if (!s->core->poll(ticket, &t)) return ME_EINVAL;
+  if (!t.done) return ME_EBUSY;
+  *queue_s = t.queue_s;
+  *service_s = t.latency_s - t.queue_s;
+  return ME_OK;
+}
+
 me_status me_server_stats(me_server s, me_server_stats_t* st) {
   if (!s || !st) return ME_EINVAL;
   me::ServerStats x = s->core->stats();

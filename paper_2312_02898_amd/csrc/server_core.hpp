@@ -39,12 +39,14 @@ struct Request {
   int32_t npar = 0;
   int64_t bytes = 0;               // device footprint
   std::chrono::steady_clock::time_point t_submit;
+  std::chrono::steady_clock::time_point t_admit;   // slot and memory granted, work launched
 };
 
 struct TicketState {
   int done = 0;
   int status = 0;
-  double latency_s = 0;
+  double latency_s = 0;   // submit -> completion
+  double queue_s = 0;     // submit -> admission (the rest of the latency is service)
 };
 
 // First-fit allocator over [0, capacity) with 256-byte granules.
@@ -178,6 +180,7 @@ class ServerCore {
     t.done = 1;
     t.status = status;
     t.latency_s = std::chrono::duration<double>(now - s.req.t_submit).count();
+    t.queue_s = std::chrono::duration<double>(s.req.t_admit - s.req.t_submit).count();
     if (status == 0) {
       ++st_.completed;
       st_.events_completed += s.req.nevt;
@@ -213,6 +216,7 @@ class ServerCore {
       if (off < 0) break;   // head-of-line: wait for memory, keep arrival order
       Slot& s = slots_[free_slot];
       s.req = queue_.front();
+      s.req.t_admit = std::chrono::steady_clock::now();
       queue_.pop_front();
       s.busy = true;
       s.off = off;

@@ -33,9 +33,10 @@ def make_stream(names, nreq, rate_hz, seed=5, nmin=256, nmax=65536):
     return arrivals, procs, moms
 
 
-def run_stream(handles, arrivals, procs, moms, budget_bytes=1 << 30, n_slots=8, timeout_s=120.0):
+def run_stream(handles, arrivals, procs, moms, budget_bytes=1 << 30, n_slots=8, timeout_s=120.0, times=None):
     """Replay the stream against a server; returns per-request latencies,
-    outputs and the wall time."""
+    outputs and the wall time.  If `times` is a list, it receives the
+    (queue_s, service_s) split of every request."""
     srv = B.me_server_create(budget_bytes, n_slots)
     outs = [np.empty(m.shape[0], dtype=np.float64) for m in moms]
     tickets = []
@@ -51,6 +52,8 @@ def run_stream(handles, arrivals, procs, moms, budget_bytes=1 << 30, n_slots=8, 
         for i, t in enumerate(tickets):
             st, l = B.me_server_wait(srv, t, timeout_s)
             status[i], lat[i] = st, l
+            if times is not None:
+                times.append(B.me_server_times(srv, t))
         wall = time.perf_counter() - t0
         stats = B.me_server_stats(srv)
     finally:

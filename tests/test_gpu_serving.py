@@ -43,8 +43,13 @@ def test_mix_equals_alone(handles, budget, slots):
     from paper_2312_02898_amd.serving import make_stream, run_stream
     print(f"[serving] budget={budget} slots={slots}", flush=True)
     arr, procs, moms = make_stream(NAMES, 48, rate_hz=2000.0, seed=5, nmin=256, nmax=16384)
-    lat, status, outs, wall, st = run_stream(handles, arr, procs, moms, budget_bytes=budget, n_slots=slots)
+    times = []
+    lat, status, outs, wall, st = run_stream(handles, arr, procs, moms, budget_bytes=budget, n_slots=slots,
+                                             times=times)
     assert (status == 0).all()
+    q = np.array([t[0] for t in times])
+    sv = np.array([t[1] for t in times])
+    assert (q >= 0).all() and (sv > 0).all() and np.allclose(q + sv, lat, rtol=0, atol=1e-9)
     assert st["completed"] == 48 and st["failed"] == 0
     assert st["peak_bytes_in_use"] <= budget and st["bytes_in_use"] == 0
     for name, m, o in zip(procs, moms, outs):
