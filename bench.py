@@ -105,8 +105,18 @@ def cpu_baseline(mom, seconds=12.0):
     t = time.perf_counter()
     ref = oracle.me("g g > t t~ g g", mom[:n], nthreads=threads)
     dt = time.perf_counter() - t
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": n / dt, "unit": "ME/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n} of the 2^20 gg>ttgg events (seed 4), all 64 helicities, FP64"}, ref, n
+            "sample": f"first {n} of the 2^20 gg>ttgg events (seed 4), all 64 helicities, FP64",
+            "per_core": n / dt / threads, "cpu_model": model, "nproc": os.cpu_count()}, ref, n
 
 
 def main():
