@@ -158,6 +158,13 @@ me_status me_compute_channels(const me_handle* handles, int32_t nchannels, const
                               const int32_t* d_channel, const double* d_alphas, int64_t nevt,
                               double* d_me, void* hip_stream);
 
+/* Debugging: with the environment variable ME_DEBUG set (not "0") when a
+ * handle is created, me_compute first checks every event on the device
+ * (finite components, E >= 0, incoming = outgoing four-momentum within 1e-9
+ * of the incoming energy; this synchronises the stream) and returns
+ * ME_EINVAL without computing if any event fails.  Off by default: the hot
+ * path does not validate. */
+
 /* Colour-summed (not averaged) |M_h|^2 of all 2^npar helicity configurations,
  * d_me_hel [nevt][2^npar], FP64.  Diagnostic; asynchronous. */
 me_status me_compute_helicities(me_handle h, const double* d_momenta, int64_t nevt,

@@ -3,6 +3,7 @@
 // vector-memory code: per-block LDS counters, one wave-level ballot per
 // channel for the stable ranks, one block for the scan over blocks.
 #include "channels.hpp"
+#include "handle.hpp"
 
 namespace me {
 namespace chan {
@@ -183,4 +184,44 @@ hipError_t scatter(const double* res, const int64_t* perm, const int32_t* channe
 }
 
 }  // namespace chan
+
+namespace {
+__global__ __launch_bounds__(256) void validate_kernel(const double* __restrict__ mom, int64_t n, int npar,
+                                                       unsigned long long* __restrict__ bad) {
+  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= n) return;
+  const double* p = mom + e * 4 * npar;
+  double bal[4] = {0, 0, 0, 0};
+  bool ok = true;
+  for (int i = 0; i < npar; ++i) {
+    for (int c = 0; c < 4; ++c) {
+      const double v = p[4 * i + c];
+      ok = ok && isfinite(v);
+      bal[c] += i < 2 ? v : -v;
+    }
+    ok = ok && p[4 * i] >= 0.0;
+  }
+  const double scale = p[0] + p[4];
+  for (int c = 0; c < 4; ++c) ok = ok && fabs(bal[c]) <= 1e-9 * scale;
+  if (!ok) atomicAdd(bad, 1ull);
+}
+__global__ void clear_u64(unsigned long long* x) { *x = 0ull; }
+}  // namespace
+
+int64_t validate_momenta(const double* d_mom, int64_t nevt, int npar, hipStream_t s) {
+  if (nevt <= 0) return 0;
+  const int64_t nb = (nevt + 255) / 256;
+  if (nb > 0x7fffffffLL) return -1;
+  unsigned long long* d_bad = nullptr;
+  if (hipMallocAsync(reinterpret_cast<void**>(&d_bad), sizeof(unsigned long long), s) != hipSuccess) return -1;
+  hipLaunchKernelGGL(clear_u64, dim3(1), dim3(1), 0, s, d_bad);
+  hipLaunchKernelGGL(validate_kernel, dim3(unsigned(nb)), dim3(256), 0, s, d_mom, nevt, npar, d_bad);
+  unsigned long long h_bad = 0;
+  hipError_t err = hipGetLastError();
+  if (err == hipSuccess) err = hipMemcpyAsync(&h_bad, d_bad, sizeof(h_bad), hipMemcpyDeviceToHost, s);
+  if (err == hipSuccess) err = hipStreamSynchronize(s);
+  (void)hipFreeAsync(d_bad, s);
+  return err == hipSuccess ? int64_t(h_bad) : -1;
+}
+
 }  // namespace me

@@ -9,6 +9,7 @@ struct me_handle_s {
   me::MeParams kp;        // kernel parameters incl. the good-helicity list
   int filtered;
   int device;
+  int debug;              // ME_DEBUG set at creation: me_compute validates its momenta
 };
 
 namespace me {
@@ -21,5 +22,11 @@ inline int mode_of(const me_sm_params& p) {
          : p.precision == ME_MIXED_MFMA16 ? ME_MODE_MIXED_MFMA16
                                           : ME_MODE_FP64;
 }
+
+// Checks every event of a batch: finite components, E >= 0 and four-momentum
+// balance (sum of incoming = sum of outgoing legs, legs 0 and 1 incoming)
+// within 1e-9 of the incoming energy.  Returns the number of bad events
+// (synchronises the stream); negative on a HIP error.
+int64_t validate_momenta(const double* d_mom, int64_t nevt, int npar, hipStream_t s);
 
 }  // namespace me

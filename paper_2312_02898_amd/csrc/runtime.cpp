@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -145,6 +146,10 @@ me_status me_create(const char* process, const me_sm_params* p, me_handle* out) 
   h->params = *p;
   h->device = dev;
   h->filtered = 0;
+  {
+    const char* dbg = std::getenv("ME_DEBUG");
+    h->debug = dbg && *dbg && std::strcmp(dbg, "0") != 0;
+  }
   const double pi = 3.14159265358979323846;
   const double ee = std::sqrt(4.0 * pi * p->alpha_em);
   const double s2 = p->sin2_thetaw, sw = std::sqrt(s2), cw = std::sqrt(1.0 - s2);
@@ -216,6 +221,13 @@ me_status me_compute(me_handle h, const double* d_momenta, int64_t nevt, double*
   if (nevt < 0) return fail(ME_EINVAL, "me_compute: nevt < 0");
   if (nevt == 0) return ME_OK;
   if (!d_momenta || !d_me) return fail(ME_EINVAL, "me_compute: null pointer");
+  if (h->debug) {
+    const int64_t bad = me::validate_momenta(d_momenta, nevt, h->proc->npar, static_cast<hipStream_t>(hip_stream));
+    if (bad < 0) return fail(ME_EHIP, "me_compute: momentum validation failed to run");
+    if (bad > 0)
+      return fail(ME_EINVAL, "me_compute: " + std::to_string(bad) +
+                                 " events with non-finite components, negative energy or unbalanced momentum");
+  }
   int rc = h->proc->launch(me::mode_of(h->params), d_momenta, nevt, d_me, nullptr, &h->kp,
                            static_cast<hipStream_t>(hip_stream));
   if (rc != 0) {

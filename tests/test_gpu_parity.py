@@ -182,3 +182,23 @@ def test_mfma_colour_sum_matches_valu(B, dev, proc, variant, med, mx):
     rel = _rel(a, b)
     print(f"  {variant} vs valu median {np.median(rel):.3e} max {rel.max():.3e}", flush=True)
     assert np.median(rel) < med and rel.max() < mx
+
+
+def test_debug_validation(B, dev, monkeypatch):
+    """With ME_DEBUG set at creation, me_compute rejects batches with
+    non-finite or unbalanced momenta (and computes valid ones)."""
+    monkeypatch.setenv("ME_DEBUG", "1")
+    me = _me(B, "ggtt", "fp64")
+    mom = config_events("ggtt", 300)
+    ok = _run(me, mom, dev)
+    assert np.isfinite(ok).all()
+    for bad in ("nan", "balance"):
+        m = mom.copy()
+        if bad == "nan":
+            m[17, 2, 1] = np.nan
+        else:
+            m[250, 3, 0] += 1e-3
+        with pytest.raises(B.MeError) as e:
+            _run(me, m, dev)
+        assert e.value.status == B.ME_EINVAL
+    me.close()
