@@ -27,6 +27,12 @@ PROCESSES = {
     "g g > t t~ g g g": 4,
     "u u~ > t t~": 5,
     "u~ u > t t~": 6,
+    "u u~ > t t~ g": 7,
+    "u~ u > t t~ g": 8,
+    "u g > t t~ u": 9,
+    "g u > t t~ u": 10,
+    "u~ g > t t~ u~": 11,
+    "g u~ > t t~ u~": 12,
 }
 
 
@@ -87,6 +93,7 @@ def lib():
         L.oracle_dressed_amp.argtypes = [i, P(Params), P(d), i, P(i), P(d)]
         L.oracle_colour_basis.argtypes = [i, P(i), P(d)]
         L.oracle_colour_matrix.argtypes = [i, P(d)]
+        L.oracle_me_gauge.argtypes = [i, P(Params), P(d), ctypes.c_int64, P(d)]
         L.oracle_uniforms.argtypes = [ctypes.c_int64, i, ctypes.c_uint64, P(d)]
         L.oracle_rambo.argtypes = [ctypes.c_int64, i, P(d), d, ctypes.c_uint64, P(d)]
         _lib = L
@@ -139,6 +146,17 @@ def me_hel(process, mom, params: Params | None = None, nthreads=0):
                              int(nthreads))
     if rc != 0:
         raise ValueError(f"oracle_me_hel failed ({rc})")
+    return out
+
+
+def me_gauge(process, mom, params: Params | None = None):
+    """Processes with one light-quark line and one gluon: |M|^2 with the
+    gluon polarisation replaced by k/k^0 (gauge invariance: zero)."""
+    p = params or default_params()
+    mom = np.ascontiguousarray(mom, dtype=np.float64)
+    out = np.empty(mom.shape[0], dtype=np.float64)
+    if lib().oracle_me_gauge(proc_id(process), ctypes.byref(p), _dp(mom), mom.shape[0], _dp(out)) != 0:
+        raise ValueError("oracle_me_gauge failed")
     return out
 
 

@@ -214,14 +214,22 @@ template <class T> struct Couplings {
   }
 };
 
-int npar_of(int proc) { return proc == 0 || proc == 5 || proc == 6 ? 4 : (proc >= 1 && proc <= 4 ? 3 + proc : -1); }
 // light quark-antiquark annihilation into t tbar (processes 5 and 6)
 bool is_qq(int proc) { return proc == 5 || proc == 6; }
+// one light-quark line, t tbar and one gluon (processes 7..12)
+bool is_qqg(int proc) { return proc >= 7 && proc <= 12; }
+int npar_of(int proc) {
+  if (proc == 0 || is_qq(proc)) return 4;
+  if (is_qqg(proc)) return 5;
+  return proc >= 1 && proc <= 4 ? 3 + proc : -1;
+}
 int ngluon_of(int proc) { return proc >= 1 && proc <= 4 ? proc + 1 : 0; }
 long factorial(int n) { long f = 1; for (int i = 2; i <= n; ++i) f *= i; return f; }
 double iden_of(int proc) {
   if (proc == 0) return 4.0;
   if (is_qq(proc)) return 36.0;   // 2 x 2 spins, 3 x 3 colours
+  if (proc == 7 || proc == 8) return 36.0;
+  if (is_qqg(proc)) return 96.0;  // quark (or antiquark) and gluon in: 2 x 2 spins, 3 x 8 colours
   int nfinal_g = ngluon_of(proc) - 2;
   return 256.0 * double(factorial(nfinal_g));
 }
@@ -274,6 +282,146 @@ template <class T> cx<T> amp_qqtt(const Couplings<T>& c, const T (*p)[4], int he
   const T s = q[0] * q[0] - q[1] * q[1] - q[2] * q[2] - q[3] * q[3];
   const cx<T> I(0, 1);
   return (-I * c.gs) * (-I * c.gs) * (-I / s) * mdot(sandwich(vb, u), sandwich(ub, v));
+}
+
+// ------------------------------------- light-quark line + t tbar + one gluon
+// Processes 7 "u u~ > t t~ g", 8 "u~ u > t t~ g", 9 "u g > t t~ u",
+// 10 "g u > t t~ u", 11 "u~ g > t t~ u~", 12 "g u~ > t t~ u~" (massless u).
+// The light line runs along the fermion arrow from its column end (u(p) of
+// an incoming quark or v(p) of an outgoing antiquark) to its row end (ubar(p)
+// of an outgoing quark or vbar(p) of an incoming antiquark); the top line
+// from v(p3) to ubar(p2).  Literal Feynman rules: quark-gluon vertex
+// -i g gamma^mu t^a, fermion propagator i(P/ + m)/(P^2 - m^2 + i m Gamma),
+// gluon propagator -i g_{mu nu}/Q^2, three-gluon vertex
+// -g f^{abc} [g^{mu nu}(k1-k2)^rho + g^{nu rho}(k2-k3)^mu + g^{rho mu}(k3-k1)^nu]
+// (all momenta incoming).  Five diagrams: the gluon on the light line at its
+// column or row end, on the top line at the t or tbar end, or on the gluon
+// exchanged between the lines.
+struct QqgLegs { int col, row, glu; bool col_in, row_in, glu_in; };
+QqgLegs qqg_legs(int proc) {
+  switch (proc) {
+    case 7: return {0, 1, 4, true, true, false};
+    case 8: return {1, 0, 4, true, true, false};
+    case 9: return {0, 4, 1, true, false, true};
+    case 10: return {1, 4, 0, true, false, true};
+    case 11: return {4, 0, 1, false, true, true};
+    default: return {4, 1, 0, false, true, true};
+  }
+}
+
+// Diagram-basis colour factors for explicit colours (r, c of the light line's
+// row and column ends, t, tb of the top line's, b of the gluon) and the 5x5
+// matrix sum_colours conj(c_D) c_D', by brute force.
+const std::vector<std::complex<double>>& qqg_colour_matrix();
+
+template <class T> M4<T> m4_scale(const M4<T>& a, cx<T> s) {
+  M4<T> r;
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) r.m[i][j] = a.m[i][j] * s;
+  return r;
+}
+template <class T> M4<T> m4_add_diag(const M4<T>& a, cx<T> s) {
+  M4<T> r = a;
+  for (int i = 0; i < 4; ++i) r.m[i][i] += s;
+  return r;
+}
+template <class T> T msq4(const T* k) { return k[0] * k[0] - k[1] * k[1] - k[2] * k[2] - k[3] * k[3]; }
+
+// Lorentz parts A_D of the five diagrams for helicity hel; gauge: replace the
+// gluon polarisation by k/k^0.
+template <class T>
+void qqg_diagrams(const Couplings<T>& c, const T (*p)[4], int proc, int hel, bool gauge, cx<T>* A) {
+  const QqgLegs L = qqg_legs(proc);
+  int lam[5];
+  for (int i = 0; i < 5; ++i) lam[i] = ((hel >> i) & 1) ? 1 : -1;
+  const cx<T> I(0, 1);
+  const T g = c.gs;
+  // external states
+  const Sp<T> colL = L.col_in ? spinor_u(p[L.col], T(0), lam[L.col]) : spinor_v(p[L.col], T(0), lam[L.col]);
+  const Sp<T> rowL = L.row_in ? bar(spinor_v(p[L.row], T(0), lam[L.row])) : bar(spinor_u(p[L.row], T(0), lam[L.row]));
+  const Sp<T> rowT = bar(spinor_u(p[2], c.mt, lam[2]));
+  const Sp<T> colT = spinor_v(p[3], c.mt, lam[3]);
+  V4<T> eps;
+  if (gauge) {
+    for (int m = 0; m < 4; ++m) eps.c[m] = p[L.glu][m] / p[L.glu][0];
+  } else {
+    eps = polvec(p[L.glu], lam[L.glu]);
+    if (!L.glu_in) eps = vconj(eps);
+  }
+  // momenta flowing into the diagram
+  T qc[4], qr[4], kg[4], qt[4], qtb[4];
+  for (int m = 0; m < 4; ++m) {
+    qc[m] = L.col_in ? p[L.col][m] : -p[L.col][m];
+    qr[m] = L.row_in ? p[L.row][m] : -p[L.row][m];
+    kg[m] = L.glu_in ? p[L.glu][m] : -p[L.glu][m];
+    qt[m] = -p[2][m];
+    qtb[m] = -p[3][m];
+  }
+  auto vtx = [&](const V4<T>& v) { return m4_scale(slash(v), -I * g); };          // -i g V/
+  auto fprop = [&](const T* P, T m, T w) {                                         // i(P/ + m)/(P^2 - m^2 + i m w)
+    const cx<T> den = cx<T>(msq4(P) - m * m, m * w);
+    return m4_scale(m4_add_diag(slash(vreal<T>(P)), cx<T>(m)), I / den);
+  };
+  auto gprop = [&](const T* Q) { return -I / msq4(Q); };
+  // t-channel top propagator: the legs on one side hold exactly one incoming leg
+  const T wtop = (c.tzero && L.glu_in) ? T(0) : c.wt;
+  // currents
+  const V4<T> JT = vscale(sandwich(rowT, colT), -I * g);
+  const V4<T> JL = vscale(sandwich(rowL, colL), -I * g);
+  T Q0[4], P1[4], P2[4], PT3[4], PT4[4], QT[4];
+  for (int m = 0; m < 4; ++m) {
+    Q0[m] = qc[m] + qr[m];            // gluon from the light line (no extra gluon on it)
+    P1[m] = qc[m] + kg[m];            // D1: along the arrow after absorbing the gluon at the column end
+    P2[m] = -qr[m] - kg[m];           // D2: along the arrow before the gluon at the row end
+    PT3[m] = -qt[m] - kg[m];          // D3: top line, gluon at the t end
+    PT4[m] = qtb[m] + kg[m];          // D4: top line, gluon at the tbar end
+    QT[m] = qt[m] + qtb[m];           // gluon into the top line's vertex from the top side
+  }
+  T Q1[4];
+  for (int m = 0; m < 4; ++m) Q1[m] = qc[m] + qr[m] + kg[m];
+  // D1, D2: gluon on the light line; exchanged gluon carries Q1
+  {
+    const Sp<T> s1 = mat_col(fprop(P1, T(0), T(0)), mat_col(vtx(eps), colL));
+    const V4<T> J1 = vscale(sandwich(rowL, s1), -I * g);
+    A[0] = mdot(J1, JT) * gprop(Q1);
+    const Sp<T> r2 = row_mat(row_mat(rowL, vtx(eps)), fprop(P2, T(0), T(0)));
+    const V4<T> J2 = vscale(sandwich(r2, colL), -I * g);
+    A[1] = mdot(J2, JT) * gprop(Q1);
+  }
+  // D3, D4: gluon on the top line; exchanged gluon carries Q0
+  {
+    const Sp<T> r3 = row_mat(row_mat(rowT, vtx(eps)), fprop(PT3, c.mt, wtop));
+    const V4<T> J3 = vscale(sandwich(r3, colT), -I * g);
+    A[2] = mdot(JL, J3) * gprop(Q0);
+    const Sp<T> s4 = mat_col(fprop(PT4, c.mt, wtop), mat_col(vtx(eps), colT));
+    const V4<T> J4 = vscale(sandwich(rowT, s4), -I * g);
+    A[3] = mdot(JL, J4) * gprop(Q0);
+  }
+  // D5: three-gluon vertex (a = light-line gluon with Q0, b = external gluon
+  // with kg, c = top-line gluon with QT; all into the vertex)
+  {
+    const V4<T> JLp = vscale(JL, gprop(Q0)), JTp = vscale(JT, gprop(QT));
+    V4<T> d12, d23, d31;
+    for (int m = 0; m < 4; ++m) {
+      d12.c[m] = Q0[m] - kg[m];
+      d23.c[m] = kg[m] - QT[m];
+      d31.c[m] = QT[m] - Q0[m];
+    }
+    A[4] = -g * (mdot(JLp, eps) * mdot(d12, JTp) + mdot(eps, JTp) * mdot(d23, JLp) + mdot(JTp, JLp) * mdot(d31, eps));
+  }
+}
+
+template <class T> T qqg_me_hel(const Couplings<T>& c, const T (*p)[4], int proc, int hel, bool gauge) {
+  cx<T> A[5];
+  qqg_diagrams(c, p, proc, hel, gauge, A);
+  const auto& C = qqg_colour_matrix();
+  T sum = 0;
+  for (int d = 0; d < 5; ++d)
+    for (int e = 0; e < 5; ++e) {
+      const std::complex<double> cde = C[size_t(d) * 5 + e];
+      sum += (std::conj(A[d]) * cx<T>(T(cde.real()), T(cde.imag())) * A[e]).real();
+    }
+  return sum;
 }
 
 // ------------------------------------------------------------------- QCD
@@ -539,6 +687,40 @@ double qq_colour_factor() {
   return v;
 }
 
+// Colour factors of the five light-line + gluon diagrams for explicit
+// colours, c_D = (t^a t^b)_{rc}(t^a)_{t tb}, (t^b t^a)_{rc}(t^a)_{t tb},
+// (t^a)_{rc}(t^b t^a)_{t tb}, (t^a)_{rc}(t^a t^b)_{t tb}, f^{abc'}(t^a)_{rc}(t^c')_{t tb}
+// (summed over a, c'), and M_{DE} = sum over r, c, t, tb, b of conj(c_D) c_E.
+const std::vector<std::complex<double>>& qqg_colour_matrix() {
+  static const std::vector<std::complex<double>> M = [] {
+    const SU3& s = su3();
+    std::vector<std::complex<double>> m(25, 0.0);
+    auto prod = [&](int a, int b, int i, int j) {
+      std::complex<double> x = 0;
+      for (int k = 0; k < 3; ++k) x += s.t[a][i][k] * s.t[b][k][j];
+      return x;
+    };
+    for (int r = 0; r < 3; ++r)
+      for (int cl = 0; cl < 3; ++cl)
+        for (int t = 0; t < 3; ++t)
+          for (int tb = 0; tb < 3; ++tb)
+            for (int b = 0; b < 8; ++b) {
+              std::complex<double> f[5] = {0, 0, 0, 0, 0};
+              for (int a = 0; a < 8; ++a) {
+                f[0] += prod(a, b, r, cl) * s.t[a][t][tb];
+                f[1] += prod(b, a, r, cl) * s.t[a][t][tb];
+                f[2] += s.t[a][r][cl] * prod(b, a, t, tb);
+                f[3] += s.t[a][r][cl] * prod(a, b, t, tb);
+                for (int c2 = 0; c2 < 8; ++c2) f[4] += s.f[a][b][c2] * s.t[a][r][cl] * s.t[c2][t][tb];
+              }
+              for (int d = 0; d < 5; ++d)
+                for (int e = 0; e < 5; ++e) m[size_t(d) * 5 + e] += std::conj(f[d]) * f[e];
+            }
+    return m;
+  }();
+  return M;
+}
+
 const std::vector<double>& colour_matrix_cached(int n) {
   static std::mutex mtx;
   static std::vector<double> cache[6];
@@ -671,6 +853,7 @@ T me_hel(int proc, const Couplings<T>& c, const T (*p)[4], int hel, const std::v
          std::vector<cx<T>>& A) {
   if (proc == 0) return std::norm(amp_eemumu(c, p, hel));
   if (is_qq(proc)) return T(qq_colour_factor()) * std::norm(amp_qqtt(c, p, hel, proc == 5 ? 0 : 1, proc == 5 ? 1 : 0));
+  if (is_qqg(proc)) return qqg_me_hel(c, p, proc, hel, false);
   int ng = ngluon_of(proc);
   QcdEvent<T> ev = qcd_setup(c, p, ng, hel, -1);
   partial_amps(c, ev, A.data());
@@ -838,7 +1021,21 @@ int oracle_rambo(int64_t nevt, int nfinal, const double* masses, double sqrt_s, 
 
 int oracle_npar(int proc) { return npar_of(proc); }
 int oracle_ncolor(int proc) {
+  if (is_qqg(proc)) return 5;   // diagram basis
   return proc == 0 || is_qq(proc) ? 1 : (npar_of(proc) < 0 ? -1 : int(factorial(ngluon_of(proc))));
+}
+
+int oracle_me_gauge(int proc, const oracle_params* p, const double* mom, int64_t nevt, double* out) {
+  if (!is_qqg(proc) || !p || nevt < 0 || (nevt > 0 && (!mom || !out))) return -1;
+  const Couplings<double> c(*p);
+  for (int64_t e = 0; e < nevt; ++e) {
+    double pp[7][4];
+    load_event(mom + size_t(e) * 5 * 4, 5, pp);
+    double tot = 0;
+    for (int h = 0; h < 32; ++h) tot += qqg_me_hel(c, pp, proc, h, true);
+    out[e] = tot / iden_of(proc);
+  }
+  return 0;
 }
 double oracle_iden(int proc) { return npar_of(proc) < 0 ? -1.0 : iden_of(proc); }
 
@@ -864,6 +1061,7 @@ int oracle_partial_amps(int proc, const oracle_params* prm, const double* mom, i
   const Couplings<double> c(*prm);
   double p[7][4];
   load_event(mom, npar, p);
+  if (is_qqg(proc)) return -1;
   if (proc == 0 || is_qq(proc)) {
     if (gauge_leg >= 0) return -1;
     std::complex<double> a = proc == 0 ? amp_eemumu(c, p, hel)

@@ -26,7 +26,9 @@
  *   process ids: 0 "e+ e- > mu+ mu-", 1 "g g > t t~", 2 "g g > t t~ g",
  *                3 "g g > t t~ g g", 4 "g g > t t~ g g g", 5 "u u~ > t t~",
  *                6 "u~ u > t t~" (massless light quark; the q qbar channels
- *                of p p > t t~ beside g g > t t~).
+ *                of p p > t t~ beside g g > t t~), 7 "u u~ > t t~ g",
+ *                8 "u~ u > t t~ g", 9 "u g > t t~ u", 10 "g u > t t~ u",
+ *                11 "u~ g > t t~ u~", 12 "g u~ > t t~ u~" (one jet).
  *   momenta:     double mom[nevt][npar][4], (E,px,py,pz) in GeV, legs 0 and 1
  *                incoming, the others outgoing, leg order = process string.
  *   helicity index h in [0, 2^npar): leg i has helicity +1 if bit i of h is
@@ -67,6 +69,10 @@ int oracle_me(int proc, const oracle_params* p, const double* mom, int64_t nevt,
 /* Colour-summed (not averaged) |M_h|^2 for every helicity h, out[nevt][2^npar]. */
 int oracle_me_hel(int proc, const oracle_params* p, const double* mom, int64_t nevt,
                   double* out, int nthreads);
+
+/* Processes 7..12: as oracle_me with the gluon's polarisation replaced by
+ * its momentum k/k^0 (gauge check: must vanish). */
+int oracle_me_gauge(int proc, const oracle_params* p, const double* mom, int64_t nevt, double* out);
 
 /* Colour-ordered partial amplitudes A(sigma) of one event at helicity h,
  * out[ncolor][2] (re, im).  For ee->mumu (one colour flow) out[0] is the full

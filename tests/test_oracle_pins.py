@@ -502,3 +502,41 @@ def test_qqbar_ttbar_closed_form(oracle_lib):
     for h in range(16):
         if ((h >> 0) & 1) == ((h >> 1) & 1):
             assert np.abs(hel[:, h]).max() <= 1e-12 * hel.sum(axis=1).max()
+
+
+QQG = ["u u~ > t t~ g", "u~ u > t t~ g", "u g > t t~ u", "g u > t t~ u", "u~ g > t t~ u~", "g u~ > t t~ u~"]
+
+
+@pytest.mark.parametrize("name", QQG)
+def test_one_jet_quark_channels_gauge_invariant(oracle_lib, name):
+    """One light-quark line, t tbar and a gluon (five diagrams incl. the
+    three-gluon vertex): with the gluon polarisation replaced by k/k^0 the
+    colour-summed |M|^2 vanishes (top width 0: a fixed width breaks gauge
+    invariance at O(Gamma/m)).  This fixes the relative signs and colour
+    factors of the five diagrams."""
+    mom = config_events("ggttg", 24)
+    p0 = oracle_lib.default_params(wt=0.0)
+    me = oracle_lib.me(name, mom, p0)
+    g = oracle_lib.me_gauge(name, mom, p0)
+    assert (me > 0).all()
+    assert np.abs(g / me).max() <= 1e-12
+
+
+def test_one_jet_quark_channels_leg_swap_and_helicity(oracle_lib):
+    """The channels with the incoming legs swapped give the same |M|^2 with
+    swapped momenta; the massless light line conserves helicity, so half of
+    the helicity configurations vanish."""
+    mom = config_events("ggttg", 16)
+    sw = np.ascontiguousarray(mom[:, [1, 0, 2, 3, 4]])
+    for a, b in (("u u~ > t t~ g", "u~ u > t t~ g"), ("u g > t t~ u", "g u > t t~ u"),
+                 ("u~ g > t t~ u~", "g u~ > t t~ u~")):
+        assert np.abs(oracle_lib.me(b, sw) / oracle_lib.me(a, mom) - 1).max() <= 1e-13
+    # u u~ > t t~ g: incoming q and qbar must have opposite helicities;
+    # u g > t t~ u: incoming and outgoing quark the same helicity
+    for name, legs, same in (("u u~ > t t~ g", (0, 1), True), ("u g > t t~ u", (0, 4), False)):
+        hel = oracle_lib.me_hel(name, mom)
+        tot = hel.sum(axis=1).max()
+        for h in range(32):
+            bit_a, bit_b = (h >> legs[0]) & 1, (h >> legs[1]) & 1
+            if (bit_a == bit_b) == same:
+                assert np.abs(hel[:, h]).max() <= 1e-12 * tot, (name, h)
