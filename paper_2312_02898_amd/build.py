@@ -23,7 +23,8 @@ GEN = os.path.join(CSRC, "gen")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libme_mi355x.so")
 
-PROCESSES = ["eemumu", "ggtt", "ggttg", "ggttgg", "ggttggg", "uutt", "uxutt"]
+PROCESSES = ["eemumu", "ggtt", "ggttg", "ggttgg", "ggttggg", "uutt", "uxutt",
+             "uuttg", "uxuttg", "ugttu", "guttu", "uxgttux", "guxttux"]
 
 HIPCC = os.environ.get("HIPCC", "hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -15,6 +15,12 @@ PROCESS_NAMES = {
     "ggttggg": "g g > t t~ g g g",
     "uutt": "u u~ > t t~",
     "uxutt": "u~ u > t t~",
+    "uuttg": "u u~ > t t~ g",
+    "uxuttg": "u~ u > t t~ g",
+    "ugttu": "u g > t t~ u",
+    "guttu": "g u > t t~ u",
+    "uxgttux": "u~ g > t t~ u~",
+    "guxttux": "g u~ > t t~ u~",
 }
 
 

@@ -32,6 +32,12 @@ PROCESS_LEGS = {
     "g g > t t~ g g g": (0.0, 0.0, 173.0, 173.0, 0.0, 0.0, 0.0),
     "u u~ > t t~": (0.0, 0.0, 173.0, 173.0),
     "u~ u > t t~": (0.0, 0.0, 173.0, 173.0),
+    "u u~ > t t~ g": (0.0, 0.0, 173.0, 173.0, 0.0),
+    "u~ u > t t~ g": (0.0, 0.0, 173.0, 173.0, 0.0),
+    "u g > t t~ u": (0.0, 0.0, 173.0, 173.0, 0.0),
+    "g u > t t~ u": (0.0, 0.0, 173.0, 173.0, 0.0),
+    "u~ g > t t~ u~": (0.0, 0.0, 173.0, 173.0, 0.0),
+    "g u~ > t t~ u~": (0.0, 0.0, 173.0, 173.0, 0.0),
 }
 
 
@@ -143,6 +149,13 @@ CONFIGS = {
     # light-quark channels of p p > t t~ (same kinematics as g g > t t~)
     "uutt": ("u u~ > t t~", 1500.0, 1 << 19, 6),
     "uxutt": ("u~ u > t t~", 1500.0, 1 << 19, 7),
+    # one-jet channels of p p > t t~ with a light quark (same kinematics as g g > t t~ g)
+    "uuttg": ("u u~ > t t~ g", 1500.0, 1 << 20, 8),
+    "uxuttg": ("u~ u > t t~ g", 1500.0, 1 << 20, 9),
+    "ugttu": ("u g > t t~ u", 1500.0, 1 << 20, 10),
+    "guttu": ("g u > t t~ u", 1500.0, 1 << 20, 11),
+    "uxgttux": ("u~ g > t t~ u~", 1500.0, 1 << 20, 12),
+    "guxttux": ("g u~ > t t~ u~", 1500.0, 1 << 20, 13),
 }
 
 

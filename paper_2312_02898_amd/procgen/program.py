@@ -51,7 +51,7 @@ FLOPS = {
     "ffv_v0_ew": 144, "ffv_vm_ew": 170, "amp_ffv_ew": 98, "amp_ffv_ew_acc": 100,
 }
 # momentum sum per extra leg, and the propagator factor per kind
-DEN_FLOPS = {"top_t": 12, "top_s": 12, "gluon": 8, "z": 12, "photon": 8}
+DEN_FLOPS = {"top_t": 12, "top_s": 12, "gluon": 8, "z": 12, "photon": 8, "quark": 8}
 
 
 @dataclass
@@ -157,7 +157,7 @@ def add_kinematics(prog: "Program", op: "Op") -> "Op":
         kind = prog.dens[m]
         if op.kind in ("ffv_fin", "ffv_fout", "ffv_vm_ew"):
             extra.append(kmom(prog, m))
-        if kind in ("top_t", "top_s"):
+        if kind in ("top_t", "top_s", "quark"):
             extra.append(den(prog, m, "D"))
         elif kind == "z":
             extra.append(den(prog, m, "D"))
@@ -475,6 +475,89 @@ def qqtt_program(quark_first: bool = True) -> Program:
     return prog
 
 
+# ---------------------------------- light-quark line + t tbar + one gluon
+QQG_CHANNELS = {
+    # name: (process, column leg, row leg, gluon leg); legs 2, 3 are t, t~
+    "uuttg": ("u u~ > t t~ g", 0, 1, 4),
+    "uxuttg": ("u~ u > t t~ g", 1, 0, 4),
+    "ugttu": ("u g > t t~ u", 0, 4, 1),
+    "guttu": ("g u > t t~ u", 1, 4, 0),
+    "uxgttux": ("u~ g > t t~ u~", 4, 0, 1),
+    "guxttux": ("g u~ > t t~ u~", 4, 1, 0),
+}
+
+
+def qqg_program(name: str) -> Program:
+    """One light-quark line, the top line and one gluon (the one-jet
+    channels of p p > t t~ with a quark).  The light line runs along the
+    fermion arrow from its column end (u of an incoming quark or v of an
+    outgoing antiquark) to its row end (ubar of an outgoing quark or vbar of
+    an incoming antiquark).  Five diagrams: the gluon on the light line at
+    its column (D1) or row (D2) end, on the top line at the t (D3) or t~ (D4)
+    end, or on the exchanged gluon (D5).
+
+    Colour, in the flow basis F1 = (t^b)_{t c} d_{r tb}, F2 = (t^b)_{r tb} d_{t c},
+    F3 = (t^b)_{t tb} d_{r c}, F4 = (t^b)_{r c} d_{t tb} (r, c: the light
+    line's row and column colours; t, tb: the top line's; b: the gluon), by
+    t^a_ij t^a_kl = (d_il d_kj - d_ij d_kl / 3) / 2 and f^{abx} t^x = -i[t^a, t^b]:
+      D1 (t^a t^b)_rc (t^a)_ttb = F1/2 - F4/6,   D2 (t^b t^a)_rc (t^a)_ttb = F2/2 - F4/6,
+      D3 (t^a)_rc (t^b t^a)_ttb = F1/2 - F3/6,   D4 (t^a)_rc (t^a t^b)_ttb = F2/2 - F3/6,
+      D5 f^{x a b} (t^a)_rc (t^x)_ttb = i (F1 - F2)/2.
+    The jamps carry 6 x these coefficients; sum_colours conj(F_k) F_l gives
+    the matrix below, and the colour denominator is 36."""
+    process, col, row, glu = QQG_CHANNELS[name]
+    leg_sign = [1, 1, -1, -1, -1]
+    iden = 36 if glu == 4 else 96
+    C = [[12, 0, 4, 4], [0, 12, 4, 4], [4, 4, 12, 0], [4, 4, 0, 12]]
+    prog = Program(name=name, process=process, npar=5, leg_sign=leg_sign, ncolor=4, colour_num=C,
+                   colour_den=36, iden=iden, n_diagrams=5)
+    col_in, row_in, glu_in = col < 2, row < 2, glu < 2
+
+    def define(nm, ops):
+        ops = [add_kinematics(prog, op) for op in ops]
+        prog.values[nm] = ops
+        prog.deps[nm] = [v for op in ops for v in op.ins if v != nm]
+        return nm
+
+    def top_kind(m):
+        return "top_t" if _incoming_count(m) == 1 else "top_s"
+
+    mc, mr, mg, mt, mtb = 1 << col, 1 << row, 1 << glu, 1 << 2, 1 << 3
+    wc = define("wC", [Op("ext_u" if col_in else "ext_v", "wC", [], {"leg": col, "light": True})])
+    wr = define("wR", [Op("ext_vbar" if row_in else "ext_ubar", "wR", [], {"leg": row, "light": True})])
+    wg = define("wG", [Op("ext_eps", "wG", [], {"leg": glu, "conj": not glu_in})])
+    wt = define("wT", [Op("ext_ubar", "wT", [], {"leg": 2})])
+    wtb = define("wTB", [Op("ext_v", "wTB", [], {"leg": 3})])
+    # gluon currents of the two lines and the three-gluon current
+    prog.dens[mc | mr] = "gluon"
+    prog.dens[mt | mtb] = "gluon"
+    prog.dens[mc | mr | mg] = "gluon"
+    jl = define("JL", [Op("ffv_v0", "JL", [wr, wc], {"m": mc | mr})])
+    jtt = define("JTT", [Op("ffv_v0", "JTT", [wt, wtb], {"m": mt | mtb})])
+    j5 = define("J5", [Op("vvv_v", "J5", [jl, wg], {"mA": mc | mr, "mB": mg, "m": mc | mr | mg})])
+    # fermion currents with the gluon absorbed
+    prog.dens[mc | mg] = "quark"
+    prog.dens[mr | mg] = "quark"
+    prog.dens[mt | mg] = top_kind(mt | mg)
+    prog.dens[mtb | mg] = top_kind(mtb | mg)
+    c1 = define("C1", [Op("ffv_fin", "C1", [wc, wg], {"m": mc | mg, "light": True})])
+    r2 = define("R2", [Op("ffv_fout", "R2", [wr, wg], {"m": mr | mg, "light": True})])
+    r3 = define("R3", [Op("ffv_fout", "R3", [wt, wg], {"m": mt | mg})])
+    c4 = define("C4", [Op("ffv_fin", "C4", [wtb, wg], {"m": mtb | mg})])
+    diagrams = [
+        ([wr, jtt, c1], [(0, 3), (3, -1)]),    # D1
+        ([r2, jtt, wc], [(1, 3), (3, -1)]),    # D2
+        ([r3, jl, wtb], [(0, 3), (2, -1)]),    # D3
+        ([wt, jl, c4], [(1, 3), (2, -1)]),     # D4
+        ([wt, j5, wtb], [(0, 3j), (1, -3j)]),  # D5
+    ]
+    for k, (ins, jam) in enumerate(diagrams):
+        a = f"a{k}"
+        ops = [Op("amp_ffv", a, list(ins), {}), Op("jamp", None, [a], {"jam": [(i, complex(c)) for i, c in jam]})]
+        prog.items.append((ops, list(ins)))
+    return prog
+
+
 # --------------------------------------------------------------- scheduling
 def _closure(prog, names):
     seen = []
@@ -733,6 +816,7 @@ def all_programs(budget=None):
     progs = [eemumu_program()] + [qcd_program(ng, share_half=SHARE_HALF.get(n, True))
                                   for ng, n in ((2, "ggtt"), (3, "ggttg"), (4, "ggttgg"), (5, "ggttggg"))]
     progs += [qqtt_program(True), qqtt_program(False)]
+    progs += [qqg_program(n) for n in QQG_CHANNELS]
     for p in progs:
         if p.name in SPLIT:
             split_program(p, SPLIT[p.name], budget)

@@ -118,7 +118,7 @@ def emu_dir(tmp_path_factory):
 
 
 @pytest.mark.parametrize("form", ["f64", "f32"])
-@pytest.mark.parametrize("proc,nevt", [("uutt", 64), ("uxutt", 64), ("ggttg", 64), ("ggttgg", 24), ("ggttggg", 3)])
+@pytest.mark.parametrize("proc,nevt", [("uutt", 64), ("uxutt", 64), ("uuttg", 48), ("ugttu", 48), ("guxttux", 48), ("ggttg", 64), ("ggttgg", 24), ("ggttggg", 3)])
 def test_generated_program_matches_oracle(oracle_lib, emu_dir, proc, nevt, form):
     """FP64 schedule: within 1e-12 of the oracle; FP32 schedule (FP32
     vertices, FP64 kinematics): median <= 1e-5, max <= 1e-3."""
