@@ -111,3 +111,37 @@ def test_empty_channel_and_errors(dev):
     assert e.value.status == B.ME_EINVAL
     other.close()
     mix.close()
+
+
+ONEJET = ["ggttg", "uuttg", "uxuttg", "ugttu", "guttu", "uxgttux", "guxttux"]
+ONEJET_NAMES = ["g g > t t~ g", "u u~ > t t~ g", "u~ u > t t~ g", "u g > t t~ u", "g u > t t~ u",
+                "u~ g > t t~ u~", "g u~ > t t~ u~"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_one_jet_channel_mix(oracle_lib, dev, precision):
+    """p p > t t~ + 1 jet: the g g and all six light-quark channels in one
+    batch at per-event alpha_s (|M|^2 ~ alpha_s^3), against the oracle."""
+    from paper_2312_02898_amd.engine import ChannelMix
+    n = 2000 + 11
+    rng = np.random.default_rng(21)
+    mom = config_events("ggttg", n)
+    ch = rng.integers(0, len(ONEJET), size=n).astype(np.int32)
+    al = ALPHAS[rng.integers(0, 3, size=n)]
+    print(f"[channels 1j] {precision} nevt={n}", flush=True)
+    mix = ChannelMix(ONEJET, precision)
+    got = mix(torch.from_numpy(mom).to(dev), torch.from_numpy(ch).to(dev),
+              torch.from_numpy(al).to(dev)).cpu().numpy()
+    ref = np.empty(n)
+    for c, name in enumerate(ONEJET_NAMES):
+        for a in ALPHAS:
+            idx = np.nonzero((ch == c) & (al == a))[0]
+            if idx.size:
+                ref[idx] = oracle_lib.me(name, mom[idx], oracle_lib.default_params(alpha_s=float(a)))
+    rel = np.abs(got / ref - 1.0)
+    print(f"  max rel {rel.max():.3e} median {np.median(rel):.3e}", flush=True)
+    if precision == "fp64":
+        assert np.median(rel) <= 1e-14 and rel.max() <= 1e-12
+    else:
+        assert np.median(rel) <= 1e-5 and rel.max() <= 1e-3
+    mix.close()

@@ -19,10 +19,12 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-PROCS = ["eemumu", "ggtt", "ggttg", "ggttgg", "uutt", "uxutt"]
+QQG = ["uuttg", "uxuttg", "ugttu", "guttu", "uxgttux", "guxttux"]
+PROCS = ["eemumu", "ggtt", "ggttg", "ggttgg", "uutt", "uxutt"] + QQG
 # events checked element-wise against the oracle (all of ee->mumu's batch)
 NCHECK = {"eemumu": 16384, "ggtt": 4096 + 37, "ggttg": 2048 + 37, "ggttgg": 1024 + 37, "uutt": 4096 + 37,
           "uxutt": 4096 + 37}
+NCHECK.update({p: 2048 + 37 for p in QQG})
 
 
 @pytest.fixture(scope="module")
