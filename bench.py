@@ -282,7 +282,24 @@ def main():
             crow[prec] = {"value": nc / dt, "unit": "ME/s", "ms": dt * 1e3}
             mix.close()
         rec["pp_ttbar_channels"] = crow
-        del mc, chn, als, oc
+        # p p > t t~ + 1 jet: g g and the six light-quark channels
+        onejet = ["ggttg", "uuttg", "uxuttg", "ugttu", "guttu", "uxgttux", "guxttux"]
+        m1 = torch.from_numpy(config_events("ggttg", nc)).to(dev)
+        ch1 = torch.from_numpy(rng.integers(0, len(onejet), size=nc).astype(np.int32)).to(dev)
+        row1 = {"nevt": nc, "channels": [PROCESS_NAMES[x] for x in onejet]}
+        for prec in ("fp64", "mixed"):
+            mix = ChannelMix(onejet, prec)
+            mix(m1, ch1, als, oc)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                mix(m1, ch1, als, oc)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / 5
+            row1[prec] = {"value": nc / dt, "unit": "ME/s", "ms": dt * 1e3}
+            mix.close()
+        rec["pp_ttbar_1jet_channels"] = row1
+        del mc, chn, als, oc, m1, ch1
 
     # HBM-bound neighbours of the path: device phase-space generation and the
     # batch-unweighting reduction, timed with events on the current stream
