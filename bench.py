@@ -359,7 +359,8 @@ def main():
     if not args.no_cpu:
         import oracle
         subsets = {"eemumu": 16384, "ggtt": 1 << 16, "ggttg": 1 << 13, "ggttgg": 1 << 11, "ggttggg": 192,
-                   "uutt": 1 << 16, "uxutt": 1 << 16}
+                   "uutt": 1 << 16, "uxutt": 1 << 16, "uuttg": 1 << 13, "uxuttg": 1 << 13, "ugttu": 1 << 13,
+                   "guttu": 1 << 13, "uxgttux": 1 << 13, "guxttux": 1 << 13}
         errs = {}
         for name, ns in subsets.items():
             mom_s = config_events(name, ns)
