@@ -134,7 +134,7 @@ def main():
                     help="only run a plain device-to-device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the engine runs on one GPU per process; --gpus must be 1"}))
         sys.exit(2)
     if args.copy_calibration:
         import torch
