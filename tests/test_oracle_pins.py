@@ -8,6 +8,7 @@ A plausible mistake anywhere in the oracle (a dropped diagram, a wrong
 sign, index or coupling, a transposed operand, a missing symmetry factor)
 fails at least one of them.
 """
+import itertools
 import math
 
 import numpy as np
@@ -540,3 +541,337 @@ def test_one_jet_quark_channels_leg_swap_and_helicity(oracle_lib):
             bit_a, bit_b = (h >> legs[0]) & 1, (h >> legs[1]) & 1
             if (bit_a == bit_b) == same:
                 assert np.abs(hel[:, h]).max() <= 1e-12 * tot, (name, h)
+
+
+def _gell_mann():
+    """t^a = lambda^a / 2 (numpy, independent of the oracle's tables)."""
+    l = np.zeros((8, 3, 3), dtype=complex)
+    l[0][0, 1] = l[0][1, 0] = 1
+    l[1][0, 1], l[1][1, 0] = -1j, 1j
+    l[2][0, 0], l[2][1, 1] = 1, -1
+    l[3][0, 2] = l[3][2, 0] = 1
+    l[4][0, 2], l[4][2, 0] = -1j, 1j
+    l[5][1, 2] = l[5][2, 1] = 1
+    l[6][1, 2], l[6][2, 1] = -1j, 1j
+    l[7] = np.diag([1, 1, -2]) / np.sqrt(3)
+    return l / 2
+
+
+def test_one_jet_soft_gluon_limit(oracle_lib):
+    """q qbar -> t tbar g as the gluon energy goes to zero: the colour-summed
+    |M|^2 tends to  -g^2 sum_{i,j} (p_i.p_j)/((p_i.k)(p_j.k)) <T_i.T_j>/<1> x
+    |M|^2(q qbar -> t tbar)  (eikonal factorisation; i = j terms give the
+    m_i^2/(p_i.k)^2 C_F of the massive tops).  The colour correlators of the
+    Born colour tensor sum_A (t^A)_{b a} (t^A)_{t tb} are computed here by
+    brute force, with colour conservation sum_i T_i = 0 checked.  This pins
+    the normalisation of the one-jet amplitude (couplings, colour sums,
+    averaging) to the closed-form-pinned zero-jet process.  Both sides run
+    at zero top width: for a soft gluon the top propagators are off shell by
+    2 p_t.k, far below m_t Gamma_t, so a finite width would switch the
+    emission from the tops off and the eikonal limit would not hold."""
+    t = _gell_mann()
+    # Born colour tensor c[a, b, t, tb]: a incoming quark, b incoming antiquark
+    c = np.einsum("Aba,Atu->abtu", t, t)
+    # colour charges (all legs read as outgoing): incoming quark -> -t^T on a,
+    # incoming antiquark -> t on b, outgoing top -> t on t, outgoing antitop -> -t^T on tb
+    def charge(i, A, x):
+        if i == 0:
+            return -np.einsum("ya,ybtu->abtu", t[A], x)
+        if i == 1:
+            return np.einsum("by,aytu->abtu", t[A], x)
+        if i == 2:
+            return np.einsum("ty,abyu->abtu", t[A], x)
+        return -np.einsum("yu,abty->abtu", t[A], x)
+    for A in range(8):
+        assert np.abs(sum(charge(i, A, c) for i in range(4))).max() < 1e-14
+    norm = np.vdot(c, c).real
+    TT = np.array([[sum(np.vdot(charge(i, A, c), charge(j, A, c)) for A in range(8)).real / norm
+                    for j in range(4)] for i in range(4)])
+
+    g2 = 4 * np.pi * 0.118
+    mt = 173.0
+    prm = oracle_lib.default_params(wt=0.0)
+    born = config_events("ggtt", 4)
+
+    def mdot(a, b):
+        return a[0] * b[0] - a[1:] @ b[1:]
+
+    def boost(p, beta):
+        b2 = beta @ beta
+        if b2 == 0:
+            return p.copy()
+        gam = 1 / np.sqrt(1 - b2)
+        bp = beta @ p[1:]
+        e = gam * (p[0] + bp)
+        v = p[1:] + ((gam - 1) * bp / b2 + gam * p[0]) * beta
+        return np.concatenate([[e], v])
+
+    rng = np.random.default_rng(3)
+    for ev in born:
+        p0, p1, p2, p3 = ev
+        n = rng.normal(size=3)
+        n /= np.linalg.norm(n)
+        dirt = p2[1:] / np.linalg.norm(p2[1:])
+        errs = []
+        for lam in (1e-2, 1e-3):
+            k = lam * np.concatenate([[1.0], n])
+            P = p0 + p1 - k
+            mp = np.sqrt(mdot(P, P))
+            es = mp / 2
+            ps = np.sqrt(es * es - mt * mt)
+            q2 = boost(np.concatenate([[es], ps * dirt]), P[1:] / P[0])
+            q3 = boost(np.concatenate([[es], -ps * dirt]), P[1:] / P[0])
+            five = np.array([[p0, p1, q2, q3, k]])
+            four = np.array([[p0, p1, q2 + 0.5 * k, q3 + 0.5 * k]])   # on the Born surface up to O(k)
+            legs = [p0, p1, q2, q3]
+            eik = 0.0
+            for i in range(4):
+                for j in range(4):
+                    eik += mdot(legs[i], legs[j]) / (mdot(legs[i], k) * mdot(legs[j], k)) * TT[i, j]
+            pred = -g2 * eik * oracle_lib.me("u u~ > t t~", four, prm)[0]
+            errs.append(abs(oracle_lib.me("u u~ > t t~ g", five, prm)[0] / pred - 1))
+        print(f"  soft-gluon limit: |ratio - 1| = {errs[0]:.2e} (k0 = 1e-2 GeV), {errs[1]:.2e} (k0 = 1e-3 GeV)")
+        # next-to-soft corrections are O(k): the error falls tenfold with the gluon energy
+        assert errs[1] < 1e-4 and errs[1] < errs[0] / 5, errs
+
+
+def _gluon_basis(t, n):
+    """Colour-flow tensors c_sigma[a_0..a_{n-1}, i_t, j_tbar] =
+    (t^{a_sigma1} ... t^{a_sigman})_{i_t j_tbar}, sigma in lexicographic order."""
+    out = []
+    for s in itertools.permutations(range(n)):
+        m = np.ones((1,) * n + (3, 3), dtype=complex) * np.eye(3)
+        for g in s:
+            sh = [1] * n + [3, 3]
+            sh[g] = 8
+            m = np.einsum("...ij,...jk->...ik", m, t.reshape(sh))
+        out.append(m)
+    return np.array(out)
+
+
+def _apply_on_axis(b, ax, mat):
+    """mat[x, y] acting on tensor axis ax of every basis tensor (axis 0 = basis index)."""
+    return np.moveaxis(np.tensordot(mat, b, axes=([1], [ax + 1])), 0, ax + 1)
+
+
+def _soft_event(born, k, masses):
+    """Add the soft momentum k to a Born event given in its centre-of-mass
+    frame: the final-state 3-momenta are scaled by one factor so that their
+    energies add up to sqrt((P_in - k)^2), then boosted to the frame of P_in - k."""
+    pin = born[0] + born[1]
+    assert np.abs(pin[1:]).max() < 1e-9 * pin[0]
+    q = pin - k
+    mq = np.sqrt(q[0] ** 2 - q[1:] @ q[1:])
+    pv = born[2:, 1:]
+    m = np.asarray(masses)
+    lo, hi = 0.0, 1.0
+    for _ in range(200):
+        xi = 0.5 * (lo + hi)
+        if np.sqrt(m * m + xi * xi * (pv * pv).sum(1)).sum() > mq:
+            hi = xi
+        else:
+            lo = xi
+    beta = q[1:] / q[0]
+    gam = 1 / np.sqrt(1 - beta @ beta)
+    out = [born[0], born[1]]
+    for mi, p in zip(m, xi * pv):
+        e = np.sqrt(mi * mi + p @ p)
+        bp = beta @ p
+        out.append(np.concatenate([[gam * (e + bp)], p + ((gam - 1) * bp / (beta @ beta) + gam * e) * beta]))
+    out.append(k)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("nglu", [0, 1, 2])
+def test_gluon_channels_soft_gluon_limit(oracle_lib, nglu):
+    """g g -> t tbar + (n+1) g with the last gluon soft factorises onto
+    g g -> t tbar + n g: the colour- and helicity-summed |M|^2 tends to
+    -g^2 sum_{i,j} (p_i.p_j)/((p_i.k)(p_j.k)) <A| T_i.T_j |A>, summed over the
+    Born helicities, with |A> the Born's partial amplitudes in the colour-flow
+    basis.  The basis tensors and the colour charges of every leg (adjoint
+    -i f for gluons, t for the top, -t^T for the antitop) are built here from
+    Gell-Mann matrices, with colour conservation checked and the Born colour
+    sum compared with the Born |M|^2.  Chained from the closed-form-pinned
+    g g -> t tbar, this pins the absolute normalisation of each extra gluon
+    (coupling, three- and four-gluon vertices, colour factors, averaging and
+    identical-particle factors).  Zero top width on both sides, as for the
+    quark channel."""
+    t = _gell_mann()
+    f = np.array([[[(-2j * np.trace(t[a] @ (t[b] @ t[c] - t[c] @ t[b]))).real for c in range(8)]
+                   for b in range(8)] for a in range(8)])
+    adj = np.array([-1j * f[c] for c in range(8)])
+    n = nglu + 2                       # gluons in the Born
+    basis = _gluon_basis(t, n)
+    nb = basis.shape[0]
+    # legs 0, 1 -> gluon axes 0, 1; leg 2 (top) -> axis n; leg 3 (antitop) -> axis n + 1;
+    # leg 4 + m -> gluon axis 2 + m
+    axes = [0, 1, n, n + 1] + [2 + m for m in range(n - 2)]
+    tt = np.zeros((n + 2, n + 2, nb, nb), dtype=complex)
+    for col in range(8):
+        q = []
+        for leg, ax in enumerate(axes):
+            if leg == 2:
+                q.append(_apply_on_axis(basis, ax, t[col]))
+            elif leg == 3:
+                q.append(-_apply_on_axis(basis, ax, t[col].T))
+            else:
+                q.append(_apply_on_axis(basis, ax, adj[col]))
+        assert np.abs(sum(q)).max() < 1e-13
+        qf = [x.reshape(nb, -1) for x in q]
+        for i in range(n + 2):
+            for j in range(n + 2):
+                tt[i, j] += qf[i].conj() @ qf[j].T
+    bf = basis.reshape(nb, -1)
+    gmat = bf.conj() @ bf.T
+
+    names = ["g g > t t~", "g g > t t~ g", "g g > t t~ g g", "g g > t t~ g g g"]
+    born_p, real_p = names[nglu], names[nglu + 1]
+    prm = oracle_lib.default_params(wt=0.0)
+    g2 = 4 * np.pi * 0.118
+
+    def mdot(a, b):
+        return a[0] * b[0] - a[1:] @ b[1:]
+
+    rng = np.random.default_rng(5)
+    for ev in config_events(["ggtt", "ggttg", "ggttgg"][nglu], 2):
+        nhat = rng.normal(size=3)
+        nhat /= np.linalg.norm(nhat)
+        born_sum = 0.0
+        errs = []
+        for lam in (1e-2, 1e-3):
+            k = lam * np.concatenate([[1.0], nhat])
+            real = _soft_event(ev, k, [173.0, 173.0] + [0.0] * nglu)
+            legs = real[:-1]
+            eik = np.array([[mdot(legs[i], legs[j]) / (mdot(legs[i], k) * mdot(legs[j], k))
+                             for j in range(n + 2)] for i in range(n + 2)])
+            corr = 0.0
+            born_sum = 0.0
+            for h in range(2 ** (n + 2)):
+                a = oracle_lib.partial_amps(born_p, ev, h, params=prm)
+                born_sum += np.vdot(a, gmat @ a).real
+                corr += np.einsum("ij,ij->", eik, np.einsum("s,ijst,t->ij", a.conj(), tt, a)).real
+            real_me = oracle_lib.me(real_p, real[None], prm)[0] * oracle_lib.iden(real_p)
+            errs.append(abs(real_me / (-g2 * corr) - 1))
+        born_me = oracle_lib.me(born_p, ev[None], prm)[0] * oracle_lib.iden(born_p)
+        assert abs(born_sum / born_me - 1) < 1e-12
+        print(f"  {real_p}: soft-gluon limit |ratio - 1| = {errs[0]:.2e}, {errs[1]:.2e}")
+        assert errs[1] < 1e-4 and errs[1] < errs[0] / 5, errs
+
+
+def _qqbar_ttbar_g_trace(p1, p2, p3, p4, k, mt, t, f, pol_sum):
+    """sum over spins, colours and gluon polarisations of |M|^2 / g_s^6 for
+    q(p1) qbar(p2) -> t(p3) tbar(p4) g(k), zero widths, by the trace
+    technique: each diagram is a 16x16 matrix on (light-line spinor) x
+    (top-line spinor) space for each gluon index mu, and the spin sum is
+    Tr[K_d (p1-slash x (p4-slash - m)) Kbar_e (p2-slash x (p3-slash + m))].
+    Feynman rules: vertex i g gamma^mu t^a, fermion propagator
+    i(p-slash + m)/(p^2 - m^2), gluon propagator -i g_{mu nu}/q^2, three-gluon
+    vertex g f^{abc}[g^{mu nu}(k-p)^rho + g^{nu rho}(p-q)^mu + g^{rho mu}(q-k)^nu]
+    with all momenta incoming.  pol_sum(mu, mu') is the gluon polarisation
+    sum.  Momenta may be crossed (negative energies): nothing here needs a
+    spinor."""
+    i2, z2 = np.eye(2), np.zeros((2, 2))
+    sig = [np.array([[0, 1], [1, 0]], complex), np.array([[0, -1j], [1j, 0]]),
+           np.array([[1, 0], [0, -1]], complex)]
+    g0 = np.block([[i2, z2], [z2, -i2]]).astype(complex)
+    gam = [g0] + [np.block([[z2, s], [-s, z2]]) for s in sig]     # Dirac representation
+    eta = np.array([1.0, -1.0, -1.0, -1.0])
+    one = np.eye(4)
+
+    def sl(p):
+        return sum(eta[m] * p[m] * gam[m] for m in range(4))
+
+    def msq(p):
+        return p[0] ** 2 - p[1:] @ p[1:]
+
+    # colour tensors c_d[j, i, t, u, a]: j incoming antiquark, i incoming quark,
+    # t top, u antitop, a emitted gluon
+    col = np.zeros((5, 3, 3, 3, 3, 8), complex)
+    for a in range(8):
+        for b in range(8):
+            col[0, ..., a] += np.einsum("ji,tu->jitu", t[b] @ t[a], t[b])
+            col[1, ..., a] += np.einsum("ji,tu->jitu", t[a] @ t[b], t[b])
+            col[2, ..., a] += np.einsum("ji,tu->jitu", t[b], t[a] @ t[b])
+            col[3, ..., a] += np.einsum("ji,tu->jitu", t[b], t[b] @ t[a])
+            for c in range(8):
+                if f[a, b, c] != 0:
+                    col[4, ..., a] += f[a, b, c] * np.einsum("ji,tu->jitu", t[b], t[c])
+    cf = col.reshape(5, -1)
+    cmat = cf @ cf.conj().T
+
+    s, q = msq(p1 + p2), p3 + p4
+    q2 = msq(q)
+    s1 = sl(p1 - k) / msq(p1 - k)
+    s2 = sl(k - p2) / msq(k - p2)
+    s3 = (sl(p3 + k) + mt * one) / (msq(p3 + k) - mt * mt)
+    s4 = (-sl(p4 + k) + mt * one) / (msq(p4 + k) - mt * mt)
+    kd = np.zeros((5, 4, 16, 16), complex)
+    # diagrams 1-4 carry (i g)^3 i (-i) = -i g^3; diagram 5 (i g)^2 (-i)^2 g = g^3
+    for mu in range(4):
+        for nu in range(4):
+            kd[0, mu] += -1j * eta[nu] * np.kron(gam[nu] @ s1 @ gam[mu], gam[nu]) / q2
+            kd[1, mu] += -1j * eta[nu] * np.kron(gam[mu] @ s2 @ gam[nu], gam[nu]) / q2
+            kd[2, mu] += -1j * eta[nu] * np.kron(gam[nu], gam[mu] @ s3 @ gam[nu]) / s
+            kd[3, mu] += -1j * eta[nu] * np.kron(gam[nu], gam[nu] @ s4 @ gam[mu]) / s
+    # gluons at the three-gluon vertex: (mu, a, -k), (nu, b, p1 + p2), (rho, c, -q)
+    ka, kb, kc = -k, p1 + p2, -q
+    g = np.diag(eta)
+    v = (np.einsum("mn,r->mnr", g, ka - kb) + np.einsum("nr,m->mnr", g, kb - kc)
+         + np.einsum("rm,n->mnr", g, kc - ka))
+    for mu, nu, rho in itertools.product(range(4), repeat=3):
+        if v[mu, nu, rho] != 0:
+            kd[4, mu] += eta[nu] * eta[rho] * v[mu, nu, rho] * np.kron(gam[nu], gam[rho]) / (s * q2)
+    gg0 = np.kron(g0, g0)
+    kbar = np.einsum("ab,dmcb,cx->dmax", gg0, kd.conj(), gg0)
+    pr = np.kron(sl(p1), sl(p4) - mt * one)
+    pl = np.kron(sl(p2), sl(p3) + mt * one)
+    tot = 0.0
+    for d, e in itertools.product(range(5), repeat=2):
+        for mu, mp in itertools.product(range(4), repeat=2):
+            w = pol_sum(mu, mp)
+            if w != 0:
+                tot += cmat[d, e] * w * np.trace(kd[d, mu] @ pr @ kbar[e, mp] @ pl)
+    return tot
+
+
+def test_one_jet_trace_technique_and_crossing(oracle_lib):
+    """All six one-jet light-quark channels against one independent
+    evaluation of q qbar -> t tbar g: literal Feynman rules, spin sums as
+    Dirac traces (no spinors, no helicities), colour by brute force over
+    explicit colour tensors, polarisation sum -g_{mu nu} (valid with a single
+    external gluon, which the k_mu k_nu sum checks).  The q g and qbar g
+    channels follow by crossing: an outgoing quark of momentum p becomes an
+    incoming antiquark of momentum -p (one fermion crossed: overall sign -1),
+    an incoming gluon of momentum p an outgoing one of momentum -p.
+    Averaging: 36 for q qbar, 96 for q g (2 x 2 spins, 3 x 8 colours)."""
+    t = _gell_mann()
+    f = np.array([[[(-2j * np.trace(t[a] @ (t[b] @ t[c] - t[c] @ t[b]))).real for c in range(8)]
+                   for b in range(8)] for a in range(8)])
+    eta = np.array([1.0, -1.0, -1.0, -1.0])
+    mt = 173.0
+    prm = oracle_lib.default_params(wt=0.0)
+    gs6 = (4 * np.pi * 0.118) ** 3
+
+    def tr(p1, p2, p3, p4, k, pol=None):
+        ps = pol or (lambda m, n: -eta[m] if m == n else 0.0)
+        return _qqbar_ttbar_g_trace(p1, p2, p3, p4, k, mt, t, f, ps)
+
+    for ev in config_events("ggttg", 4):
+        pa, pb, p3, p4, p5 = ev
+        direct = tr(pa, pb, p3, p4, p5)
+        kl = eta * p5
+        gauge = tr(pa, pb, p3, p4, p5, lambda m, n: kl[m] * kl[n])
+        assert abs(gauge) <= 1e-12 * p5[0] ** 2 * abs(direct)
+        assert abs(direct.imag) <= 1e-14 * abs(direct.real)
+        want = {
+            "u u~ > t t~ g": direct,
+            "u~ u > t t~ g": tr(pb, pa, p3, p4, p5),
+            "u g > t t~ u": -tr(pa, -p5, p3, p4, -pb),
+            "g u > t t~ u": -tr(pb, -p5, p3, p4, -pa),
+            "u~ g > t t~ u~": -tr(-p5, pa, p3, p4, -pb),
+            "g u~ > t t~ u~": -tr(-p5, pb, p3, p4, -pa),
+        }
+        for name, w in want.items():
+            got = oracle_lib.me(name, ev[None], prm)[0]
+            expect = w.real * gs6 / oracle_lib.iden(name)
+            assert abs(got / expect - 1) <= 1e-12, (name, got, expect)
