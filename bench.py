@@ -33,8 +33,8 @@ FP64_VECTOR_PEAK = 78.6e12    # MI355X fp64 vector FLOP/s
 # the kernel source they were taken on (digest below); null otherwise.
 PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 MEASURED_TRAFFIC = {
-    "valu": {"digest": "3c1517fb3af7dbb0", "fetch_kib": 99182, "write_kib": 8192},
-    "mfma_f16_hilo": {"digest": "be884037613c3f44", "fetch_kib": 99158, "write_kib": 100937},
+    "valu": {"digest": "038f221b6f157c24", "fetch_kib": 99109, "write_kib": 8192},
+    "mfma_f16_hilo": {"digest": "6fd811bd4b12f87c", "fetch_kib": 99089, "write_kib": 8192},
 }
 
 
@@ -64,7 +64,7 @@ def kernel_digest(variant):
     for f in files:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
-    h.update(" ".join(pb.FLAGS[:-4]).encode())
+    h.update(" ".join(pb.FLAGS[:-4] + pb.KERNEL_FLAGS).encode())
     return h.hexdigest()[:16]
 
 

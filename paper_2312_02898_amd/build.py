@@ -33,6 +33,17 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # spill VGPRs to AGPRs before scratch memory
          "-mllvm", "-amdgpu-spill-vgpr-to-agpr=1",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
+# Generated process kernels only.  Their vertex algebra multiplies and adds
+# components that are structurally zero (the time component of a massless
+# polarisation vector, the imaginary part of a real propagator factor):
+# under strict IEEE rules x*0 and x+0 must be kept (x could be a NaN or an
+# infinity, the zero could be negative).  No value in these kernels is
+# infinite or NaN for physical momenta, so the compiler may fold them; the
+# flags permit no reassociation.  (The host-side NaN checks live in other
+# units.)  Adding -freciprocal-math to these two cost one FP32 part kernel
+# of g g > t t~ g g g its accuracy (median error against FP64 5e-6 instead
+# of 1e-7; any two of the three flags are fine), so it stays off.
+KERNEL_FLAGS = ["-fno-signed-zeros", "-ffinite-math-only"]
 
 
 def _digest(paths, extra=""):
@@ -43,14 +54,15 @@ def _digest(paths, extra=""):
     return h.hexdigest()[:16]
 
 
-def _compile(src, deps):
+def _compile(src, deps, extra=()):
     os.makedirs(OBJ, exist_ok=True)
     base = os.path.splitext(os.path.basename(src))[0]
-    tag = _digest([src] + deps, " ".join(FLAGS))
+    flags = FLAGS + list(extra)
+    tag = _digest([src] + deps, " ".join(flags))
     obj = os.path.join(OBJ, f"{base}-{tag}.o")
     if not os.path.exists(obj):
         tmp = obj + ".tmp"
-        cmd = [HIPCC] + FLAGS + ["-c", src, "-o", tmp]
+        cmd = [HIPCC] + flags + ["-c", src, "-o", tmp]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr[-4000:]}")
@@ -66,7 +78,7 @@ def build(processes=None, jobs=None, verbose=True) -> str:
     hdrs = [os.path.join(CSRC, f) for f in ("helas.hpp", "kernels.hpp", "me_types.h", "colour_mfma.hpp", "split.hpp")]
     table = os.path.join(GEN, "process_table.inc")
     # a part kernel of a split process, <name>__<form>_<j>.hip, shares <name>_proc.inc
-    units = [(s, hdrs + [os.path.join(GEN, os.path.basename(s)[:-4].split("__")[0] + "_proc.inc")])
+    units = [(s, hdrs + [os.path.join(GEN, os.path.basename(s)[:-4].split("__")[0] + "_proc.inc")], KERNEL_FLAGS)
              for s in srcs]
     units.append((os.path.join(CSRC, "runtime.cpp"), hdrs + [table, os.path.join(ROOT, "include", "me.h"),
                                                              os.path.join(CSRC, "channels.hpp"),
