@@ -57,6 +57,11 @@ template <class T> __device__ __forceinline__ mom<T> to_mom(const double* K) {
 __device__ __forceinline__ double msq(const double* K) {
   return K[0] * K[0] - K[1] * K[1] - K[2] * K[2] - K[3] * K[3];
 }
+// K^2 from light-cone components along the beam axis: K+ = K0 + K3,
+// K- = K0 - K3.
+__device__ __forceinline__ double msq_lc(double kp, double km, double kx, double ky) {
+  return kp * km - kx * kx - ky * ky;
+}
 
 // Minkowski product of complex 4-vectors (no conjugation).
 template <class T> __device__ __forceinline__ cx<T> dot(const wf<T>& a, const wf<T>& b) {

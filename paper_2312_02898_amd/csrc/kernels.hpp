@@ -21,9 +21,9 @@ namespace me {
 template <class T> __device__ __forceinline__ mom<T> neg(const mom<T>& k) {
   return mom<T>{{-k.k[0], -k.k[1], -k.k[2], -k.k[3]}};
 }
-// 1/(K^2 - m^2 + i m w), formed in FP64 and rounded to T.
-template <class T> __device__ __forceinline__ cx<T> prop_den(const double* K, double m, double w) {
-  const double a = msq(K) - m * m, b = m * w;
+// 1/(K^2 - m^2 + i m w) from the invariant K^2, formed in FP64 and rounded to T.
+template <class T> __device__ __forceinline__ cx<T> prop_den(double k2, double m, double w) {
+  const double a = k2 - m * m, b = m * w;
   const double r = 1.0 / (a * a + b * b);
   return cx<T>{T(a * r), T(-b * r)};
 }

@@ -45,8 +45,8 @@ MAIN = r"""
 #include "me_types.h"
 namespace me {
 template <class T> inline mom<T> neg(const mom<T>& k) { return mom<T>{{-k.k[0], -k.k[1], -k.k[2], -k.k[3]}}; }
-template <class T> inline cx<T> prop_den(const double* K, double m, double w) {
-  const double a = msq(K) - m * m, b = m * w;
+template <class T> inline cx<T> prop_den(double k2, double m, double w) {
+  const double a = k2 - m * m, b = m * w;
   const double r = 1.0 / (a * a + b * b);
   return cx<T>{T(a * r), T(-b * r)};
 }

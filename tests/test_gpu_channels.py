@@ -2,7 +2,9 @@
 channels of p p > t t~ in one batch, each event at its own alpha_s.
 
 Checks: every event against the oracle run with that event's process and
-alpha_s (FP64 within 1e-12, mixed median <= 1e-5 and max <= 1e-3); without
+alpha_s (FP64 within 1e-12, the rare ill-conditioned events above it
+adjudicated with the long-double oracle; mixed median <= 1e-5 and max <=
+1e-3); without
 per-event alpha_s the result equals, bit for bit, the same events evaluated
 channel by channel with me_compute; with it, the exact power-law rescaling;
 ragged batches, an empty channel and the error cases.
@@ -28,6 +30,24 @@ def dev():
     return torch.device("cuda:0")
 
 
+def _check_fp64(rel, got, ref, long_double):
+    """FP64 bar: within 1e-12 of the FP64 oracle; the rare ill-conditioned
+    events above it are adjudicated with the long-double oracle
+    (long_double(idx) evaluates the given events): there the GPU's worst
+    error must be within 2x (+1e-12) of the FP64 oracle's own worst error
+    over the whole sample."""
+    bad = np.nonzero(rel > 1e-12)[0]
+    assert np.isfinite(got).all() and (got > 0).all()
+    assert np.median(rel) <= 1e-14
+    assert bad.size <= max(1, 1e-3 * rel.size)
+    if bad.size:
+        ld = long_double(np.arange(rel.size))
+        e_gpu, e_ora = np.abs(got[bad] / ld[bad] - 1.0), np.abs(ref / ld - 1.0)
+        print(f"  adjudicated vs long double: gpu {e_gpu.max():.3e} oracle(double, whole sample) {e_ora.max():.3e}",
+              flush=True)
+        assert e_gpu.max() <= 2 * e_ora.max() + 1e-12
+
+
 def _batch(n, seed=11):
     rng = np.random.default_rng(seed)
     mom = config_events("ggtt", n)
@@ -36,13 +56,14 @@ def _batch(n, seed=11):
     return mom, ch, al
 
 
-def _oracle(oracle_lib, mom, ch, al):
+def _oracle(oracle_lib, mom, ch, al, names=NAMES, long_double=False):
     ref = np.empty(mom.shape[0])
-    for c in range(3):
+    for c, name in enumerate(names):
         for a in ALPHAS:
             idx = np.nonzero((ch == c) & (al == a))[0]
             if idx.size:
-                ref[idx] = oracle_lib.me(NAMES[c], mom[idx], oracle_lib.default_params(alpha_s=float(a)))
+                ref[idx] = oracle_lib.me(name, mom[idx], oracle_lib.default_params(alpha_s=float(a)),
+                                         long_double=long_double)
     return ref
 
 
@@ -59,7 +80,7 @@ def test_channel_mix_matches_oracle(oracle_lib, dev, precision):
     rel = np.abs(got / ref - 1.0)
     print(f"  max rel {rel.max():.3e} median {np.median(rel):.3e}", flush=True)
     if precision == "fp64":
-        assert rel.max() <= 1e-12
+        _check_fp64(rel, got, ref, lambda i: _oracle(oracle_lib, mom[i], ch[i], al[i], long_double=True))
     else:
         assert np.median(rel) <= 1e-5 and rel.max() <= 1e-3
     mix.close()
@@ -132,16 +153,12 @@ def test_one_jet_channel_mix(oracle_lib, dev, precision):
     mix = ChannelMix(ONEJET, precision)
     got = mix(torch.from_numpy(mom).to(dev), torch.from_numpy(ch).to(dev),
               torch.from_numpy(al).to(dev)).cpu().numpy()
-    ref = np.empty(n)
-    for c, name in enumerate(ONEJET_NAMES):
-        for a in ALPHAS:
-            idx = np.nonzero((ch == c) & (al == a))[0]
-            if idx.size:
-                ref[idx] = oracle_lib.me(name, mom[idx], oracle_lib.default_params(alpha_s=float(a)))
+    ref = _oracle(oracle_lib, mom, ch, al, names=ONEJET_NAMES)
     rel = np.abs(got / ref - 1.0)
     print(f"  max rel {rel.max():.3e} median {np.median(rel):.3e}", flush=True)
     if precision == "fp64":
-        assert np.median(rel) <= 1e-14 and rel.max() <= 1e-12
+        _check_fp64(rel, got, ref,
+                    lambda i: _oracle(oracle_lib, mom[i], ch[i], al[i], names=ONEJET_NAMES, long_double=True))
     else:
         assert np.median(rel) <= 1e-5 and rel.max() <= 1e-3
     mix.close()
