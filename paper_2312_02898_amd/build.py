@@ -40,10 +40,16 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 # infinity, the zero could be negative).  No value in these kernels is
 # infinite or NaN for physical momenta, so the compiler may fold them; the
 # flags permit no reassociation.  (The host-side NaN checks live in other
-# units.)  Adding -freciprocal-math to these two cost one FP32 part kernel
-# of g g > t t~ g g g its accuracy (median error against FP64 5e-6 instead
-# of 1e-7; any two of the three flags are fine), so it stays off.
+# units.)  Not for the FP32 part kernels of the split form: there these
+# flags (and -freciprocal-math with them) gave wrong results in single part
+# kernels of some schedules (median error against FP64 up to 2e-4), while
+# the same generated code is exact without them, on the GPU and in a host
+# build under the sanitizers.
 KERNEL_FLAGS = ["-fno-signed-zeros", "-ffinite-math-only"]
+
+
+def kernel_flags(src):
+    return [] if "__f32_" in os.path.basename(src) else KERNEL_FLAGS
 
 
 def _digest(paths, extra=""):
@@ -78,7 +84,7 @@ def build(processes=None, jobs=None, verbose=True) -> str:
     hdrs = [os.path.join(CSRC, f) for f in ("helas.hpp", "kernels.hpp", "me_types.h", "colour_mfma.hpp", "split.hpp")]
     table = os.path.join(GEN, "process_table.inc")
     # a part kernel of a split process, <name>__<form>_<j>.hip, shares <name>_proc.inc
-    units = [(s, hdrs + [os.path.join(GEN, os.path.basename(s)[:-4].split("__")[0] + "_proc.inc")], KERNEL_FLAGS)
+    units = [(s, hdrs + [os.path.join(GEN, os.path.basename(s)[:-4].split("__")[0] + "_proc.inc")], kernel_flags(s))
              for s in srcs]
     units.append((os.path.join(CSRC, "runtime.cpp"), hdrs + [table, os.path.join(ROOT, "include", "me.h"),
                                                              os.path.join(CSRC, "channels.hpp"),

@@ -849,7 +849,7 @@ MIXED_MFMA = set()
 # processes whose colour flows do not fit in registers: per arithmetic type
 # the wavefunction budget (FP64 dwords), the number of jamp accumulators a
 # lane holds at once and the number of parts.
-SPLIT = {"ggttggg": {"f64": (288, 32, 12), "f32": (384, 64, 8)}}
+SPLIT = {"ggttggg": {"f64": (288, 32, 12), "f32": (384, 40, 8)}}
 
 
 def split_program(p: Program, cfg: dict, budget=None) -> Program:
