@@ -33,23 +33,11 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # spill VGPRs to AGPRs before scratch memory
          "-mllvm", "-amdgpu-spill-vgpr-to-agpr=1",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
-# Generated process kernels only.  Their vertex algebra multiplies and adds
-# components that are structurally zero (the time component of a massless
-# polarisation vector, the imaginary part of a real propagator factor):
-# under strict IEEE rules x*0 and x+0 must be kept (x could be a NaN or an
-# infinity, the zero could be negative).  No value in these kernels is
-# infinite or NaN for physical momenta, so the compiler may fold them; the
-# flags permit no reassociation.  (The host-side NaN checks live in other
-# units.)  Not for the FP32 part kernels of the split form: there these
-# flags (and -freciprocal-math with them) gave wrong results in single part
-# kernels of some schedules (median error against FP64 up to 2e-4), while
-# the same generated code is exact without them, on the GPU and in a host
-# build under the sanitizers.
-KERNEL_FLAGS = ["-fno-signed-zeros", "-ffinite-math-only"]
-
-
-def kernel_flags(src):
-    return [] if "__f32_" in os.path.basename(src) else KERNEL_FLAGS
+# No fast-math flags.  -fno-signed-zeros -ffinite-math-only on the generated
+# kernels let the compiler fold the products and sums with structurally zero
+# components (x*0, x+0) and made them 10-30 % faster, but some schedules of
+# four kernels (FP32 and FP64, whole-process and split parts) then gave
+# wrong results that the same code without the flags does not give.
 
 
 def _digest(paths, extra=""):
@@ -60,15 +48,14 @@ def _digest(paths, extra=""):
     return h.hexdigest()[:16]
 
 
-def _compile(src, deps, extra=()):
+def _compile(src, deps):
     os.makedirs(OBJ, exist_ok=True)
     base = os.path.splitext(os.path.basename(src))[0]
-    flags = FLAGS + list(extra)
-    tag = _digest([src] + deps, " ".join(flags))
+    tag = _digest([src] + deps, " ".join(FLAGS))
     obj = os.path.join(OBJ, f"{base}-{tag}.o")
     if not os.path.exists(obj):
         tmp = obj + ".tmp"
-        cmd = [HIPCC] + flags + ["-c", src, "-o", tmp]
+        cmd = [HIPCC] + FLAGS + ["-c", src, "-o", tmp]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr[-4000:]}")
@@ -84,7 +71,7 @@ def build(processes=None, jobs=None, verbose=True) -> str:
     hdrs = [os.path.join(CSRC, f) for f in ("helas.hpp", "kernels.hpp", "me_types.h", "colour_mfma.hpp", "split.hpp")]
     table = os.path.join(GEN, "process_table.inc")
     # a part kernel of a split process, <name>__<form>_<j>.hip, shares <name>_proc.inc
-    units = [(s, hdrs + [os.path.join(GEN, os.path.basename(s)[:-4].split("__")[0] + "_proc.inc")], kernel_flags(s))
+    units = [(s, hdrs + [os.path.join(GEN, os.path.basename(s)[:-4].split("__")[0] + "_proc.inc")])
              for s in srcs]
     units.append((os.path.join(CSRC, "runtime.cpp"), hdrs + [table, os.path.join(ROOT, "include", "me.h"),
                                                              os.path.join(CSRC, "channels.hpp"),
