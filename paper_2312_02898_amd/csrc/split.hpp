@@ -59,6 +59,13 @@ __device__ __forceinline__ void jw_add(cx<T>* jw, int64_t off, cx<T> v) {
 template <class P, class T, int J>
 __global__ __launch_bounds__(256) void me_part_kernel(const double* __restrict__ mom, int64_t ne, int h0,
                                                       cx<T>* __restrict__ X, int64_t ne_pad, const MeParams prm) {
+  // jamp accumulators of the part when its schedule keeps them in LDS: lane
+  // l's slots are a row of NQP (odd) complex values at qbuf[l * NQP], so
+  // every slot is a small immediate offset from the lane's base, and eight
+  // consecutive lanes' 16-byte accesses fall in distinct groups of banks
+  constexpr int NQ = sizeof(T) == 8 ? P::QLDS_F64 : P::QLDS_F32;
+  constexpr int NQP = NQ > 0 ? (NQ | 1) : 1;
+  __shared__ cx<T> qbuf[NQP * 256];
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= ne) return;
   const int hc = blockIdx.y;
@@ -70,7 +77,7 @@ __global__ __launch_bounds__(256) void me_part_kernel(const double* __restrict__
     const double2 a = src[2 * i], b = src[2 * i + 1];
     p[i][0] = a.x; p[i][1] = a.y; p[i][2] = b.x; p[i][3] = b.y;
   }
-  P::template part<T, J>(p, hel, prm, X + int64_t(hc) * P::NCOLOR * ne_pad + e, ne_pad);
+  P::template part<T, J>(p, hel, prm, X + int64_t(hc) * P::NCOLOR * ne_pad + e, ne_pad, qbuf + threadIdx.x * NQP);
 }
 
 // Host launcher of one part kernel (each part is compiled in a translation

@@ -848,15 +848,19 @@ MIXED_MFMA = set()
 # Split form (jamps in a workspace, amplitudes in several kernels) for the
 # processes whose colour flows do not fit in registers: per arithmetic type
 # the wavefunction budget (FP64 dwords), the number of jamp accumulators a
-# lane holds at once and the number of parts.
-SPLIT = {"ggttggg": {"f64": (288, 32, 12), "f32": (384, 40, 8)}}
+# lane holds at once, the number of parts and (optional) whether the
+# accumulators live in LDS instead of registers.
+SPLIT = {"ggttggg": {"f64": (288, 36, 12, True), "f32": (384, 40, 8)}}
 
 
 def split_program(p: Program, cfg: dict, budget=None) -> Program:
     p.split = True
     p.jamps_in_memory = True
     for tag in ("f32", "f64"):
-        b, jcap, nparts = cfg[tag]
+        b, jcap, nparts = cfg[tag][:3]
+        # optional fourth entry: the jamp accumulators live in LDS (jcap
+        # slots per lane) instead of registers
+        setattr(p, f"qlds_{tag}", jcap if len(cfg[tag]) > 3 and cfg[tag][3] else 0)
         p.jamp_capacity = jcap
         parts = schedule_parts(p, budget if budget is not None else b, nparts, iters=2)
         setattr(p, f"parts_{tag}", parts)

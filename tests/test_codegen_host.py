@@ -59,7 +59,10 @@ using P = PROC;
 using T = EMU_T;
 template <int J, class Q = P> void parts(const double (&p)[P::NPAR][4], unsigned h, const MeParams& prm, cx<T>* X) {
   constexpr int N = sizeof(T) == 8 ? Q::NPARTS_F64 : Q::NPARTS_F32;
-  if constexpr (J < N) { Q::template part<T, J>(p, h, prm, X, 1); parts<J + 1, Q>(p, h, prm, X); }
+  constexpr int NQ = sizeof(T) == 8 ? Q::QLDS_F64 : Q::QLDS_F32;
+  // stands in for the part kernel's LDS jamp slots (this lane's row)
+  static cx<T> qb[NQ > 0 ? NQ : 1];
+  if constexpr (J < N) { Q::template part<T, J>(p, h, prm, X, 1, qb); parts<J + 1, Q>(p, h, prm, X); }
 }
 // a template, so that the branch for the other form is discarded
 template <class Q>
