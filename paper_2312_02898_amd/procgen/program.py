@@ -822,6 +822,7 @@ def all_programs(budget=None):
             split_program(p, SPLIT[p.name], budget)
             continue
         p.fp64_lds_jamps = p.name in FP64_LDS_JAMPS
+        p.f32_lds_jamps = p.name in F32_LDS_JAMPS
         p.mixed_mfma = p.name in MIXED_MFMA
         b64, i64 = DEFAULT_SCHEDULE_F64.get(p.name, (256, 4))
         b32, i32 = DEFAULT_SCHEDULE_F32.get(p.name, (512, 4))
@@ -841,6 +842,8 @@ SHARE_HALF = {"ggttg": False, "ggttgg": False, "ggttggg": True}
 # FP64 forms that keep their jamps in LDS (frees 4 registers per colour flow
 # for the wavefunction schedule; gg -> t tbar gg FP64 91 -> 79 ms per 2^20)
 FP64_LDS_JAMPS = {"ggttgg"}
+# the same for the mixed form's vector-ALU kernel
+F32_LDS_JAMPS = set()
 # processes whose default mixed form (ME_MIXED) sums colours on FP16 hi+lo
 # MFMA; the others use the vector ALU (chosen by measurement)
 MIXED_MFMA = set()

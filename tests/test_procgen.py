@@ -121,3 +121,31 @@ def test_every_colour_string_reached():
             if op.kind == "jamp":
                 seen |= {i for i, _ in op.prm["jam"]}
     assert seen == set(range(24))
+
+
+def test_split_lds_accumulators_fit_and_are_written_back():
+    """The FP64 parts of the split form keep their jamp accumulators in LDS:
+    the emitter gives each live accumulator a slot of the lane's LDS row and
+    frees it at the write-back (it raises if a part ends with one still in
+    LDS), at most jcap + 1 slots are live (an accumulator is added before
+    the eviction it causes), every jamp reaches the workspace, and the part
+    kernel's buffer (256 lanes x an odd row of 16-byte slots) fits the
+    160 KB of LDS of a gfx950 workgroup."""
+    from paper_2312_02898_amd.procgen import codegen
+    cfg = program.SPLIT["ggttggg"]
+    p = program.qcd_program(5, share_half=program.SHARE_HALF["ggttggg"])
+    p.name = "ggttggg"
+    program.split_program(p, cfg)
+    src = codegen.emit_proc_struct(p)
+    jcap = cfg["f64"][1]
+    nq = p.qslots_f64
+    assert cfg["f64"][3] and 0 < nq <= jcap + 1
+    assert f"QLDS_F64 = {nq};" in src
+    assert 256 * (nq | 1) * 16 <= 160 * 1024
+    # every slot index used in the FP64 parts is below the buffer's slot count
+    f64 = src[src.index("part_f64_0"):src.index("part_f32_0")]
+    slots = {int(x) for x in re.findall(r"\bq\[(\d+)\]", f64)}
+    assert slots and max(slots) < nq
+    # FP32 parts keep registers: no LDS slots there
+    f32 = src[src.index("part_f32_0"):src.index("static void part(")]
+    assert not re.findall(r"\bq\[\d+\]", f32) and p.qslots_f32 == 0
