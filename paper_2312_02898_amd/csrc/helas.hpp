@@ -48,8 +48,67 @@ template <class T> __device__ __forceinline__ cx<T> cfma(cx<T> a, cx<T> b, cx<T>
   return {a.r * b.r - a.i * b.i + c.r, a.r * b.i + a.i * b.r + c.i};
 }
 
-template <class T> struct wf { cx<T> c[4]; };   // spinor or vector wavefunction
+template <class T> struct wf {                   // spinor or vector wavefunction
+  using value_type = T;
+  cx<T> c[4];
+};
 template <class T> struct mom { T k[4]; };      // real momentum in arithmetic type T
+
+// ------------------------------------------------ structurally known zeros
+// An external massless vector has a zero time component and a real z
+// component in the helicity basis used here (ext_eps).  Strict IEEE
+// arithmetic may not drop x*0 or x+0 (x could be NaN or infinite, the zero
+// negative), so these components are carried as types instead: zero_t is an
+// exact 0, re<T> a complex number whose imaginary part is exactly 0.  The
+// vector vertices below read their vector operands through comp<M>(), so the
+// terms such a component removes are never evaluated.
+struct zero_t {};
+template <class T> struct re { T r; };
+
+template <class T> struct epsw {                 // external massless vector (0, c1, c2, c3 real)
+  using value_type = T;
+  cx<T> c1, c2;
+  T c3;
+};
+
+template <int M, class T> __device__ __forceinline__ cx<T> comp(const wf<T>& w) { return w.c[M]; }
+template <int M, class T> __device__ __forceinline__ auto comp(const epsw<T>& w) {
+  if constexpr (M == 0) return zero_t{};
+  else if constexpr (M == 1) return w.c1;
+  else if constexpr (M == 2) return w.c2;
+  else return re<T>{w.c3};
+}
+
+__device__ __forceinline__ zero_t operator*(zero_t, zero_t) { return {}; }
+template <class X> __device__ __forceinline__ zero_t operator*(zero_t, const X&) { return {}; }
+template <class X> __device__ __forceinline__ zero_t operator*(const X&, zero_t) { return {}; }
+__device__ __forceinline__ zero_t operator+(zero_t, zero_t) { return {}; }
+template <class X> __device__ __forceinline__ X operator+(zero_t, const X& x) { return x; }
+template <class X> __device__ __forceinline__ X operator+(const X& x, zero_t) { return x; }
+__device__ __forceinline__ zero_t operator-(zero_t, zero_t) { return {}; }
+template <class X> __device__ __forceinline__ X operator-(zero_t, const X& x) { return -x; }
+template <class X> __device__ __forceinline__ X operator-(const X& x, zero_t) { return x; }
+__device__ __forceinline__ zero_t operator-(zero_t) { return {}; }
+__device__ __forceinline__ zero_t mul_i(zero_t) { return {}; }
+__device__ __forceinline__ zero_t mul_mi(zero_t) { return {}; }
+
+template <class T> __device__ __forceinline__ re<T> operator-(re<T> a) { return {-a.r}; }
+template <class T> __device__ __forceinline__ re<T> operator+(re<T> a, re<T> b) { return {a.r + b.r}; }
+template <class T> __device__ __forceinline__ re<T> operator-(re<T> a, re<T> b) { return {a.r - b.r}; }
+template <class T> __device__ __forceinline__ re<T> operator*(re<T> a, re<T> b) { return {a.r * b.r}; }
+template <class T> __device__ __forceinline__ re<T> operator*(T s, re<T> a) { return {s * a.r}; }
+template <class T> __device__ __forceinline__ re<T> operator*(re<T> a, T s) { return {a.r * s}; }
+template <class T> __device__ __forceinline__ cx<T> operator*(re<T> a, cx<T> b) { return {a.r * b.r, a.r * b.i}; }
+template <class T> __device__ __forceinline__ cx<T> operator*(cx<T> b, re<T> a) { return {b.r * a.r, b.i * a.r}; }
+template <class T> __device__ __forceinline__ cx<T> operator+(re<T> a, cx<T> b) { return {a.r + b.r, b.i}; }
+template <class T> __device__ __forceinline__ cx<T> operator+(cx<T> b, re<T> a) { return {b.r + a.r, b.i}; }
+template <class T> __device__ __forceinline__ cx<T> operator-(re<T> a, cx<T> b) { return {a.r - b.r, -b.i}; }
+template <class T> __device__ __forceinline__ cx<T> operator-(cx<T> b, re<T> a) { return {b.r - a.r, b.i}; }
+
+// Widening to a full complex number.
+template <class T> __device__ __forceinline__ cx<T> as_cx(cx<T> x) { return x; }
+template <class T> __device__ __forceinline__ cx<T> as_cx(re<T> x) { return {x.r, T(0)}; }
+template <class T> __device__ __forceinline__ cx<T> as_cx(zero_t) { return {T(0), T(0)}; }
 
 template <class T> __device__ __forceinline__ mom<T> to_mom(const double* K) {
   return mom<T>{{T(K[0]), T(K[1]), T(K[2]), T(K[3])}};
@@ -64,17 +123,15 @@ __device__ __forceinline__ double msq_lc(double kp, double km, double kx, double
 }
 
 // Minkowski product of complex 4-vectors (no conjugation).
-template <class T> __device__ __forceinline__ cx<T> dot(const wf<T>& a, const wf<T>& b) {
-  cx<T> s = a.c[0] * b.c[0];
-  s = s - a.c[1] * b.c[1];
-  s = s - a.c[2] * b.c[2];
-  s = s - a.c[3] * b.c[3];
-  return s;
+// Either operand may be a wf or an epsw.
+template <class A, class B> __device__ __forceinline__ cx<typename A::value_type> dot(const A& a, const B& b) {
+  using T = typename A::value_type;
+  return as_cx<T>(((comp<0>(a) * comp<0>(b) - comp<1>(a) * comp<1>(b)) - comp<2>(a) * comp<2>(b)) -
+                  comp<3>(a) * comp<3>(b));
 }
 // Minkowski product of a real momentum with a complex vector.
-template <class T> __device__ __forceinline__ cx<T> dot(const mom<T>& k, const wf<T>& b) {
-  return cx<T>{k.k[0] * b.c[0].r - k.k[1] * b.c[1].r - k.k[2] * b.c[2].r - k.k[3] * b.c[3].r,
-               k.k[0] * b.c[0].i - k.k[1] * b.c[1].i - k.k[2] * b.c[2].i - k.k[3] * b.c[3].i};
+template <class T, class W> __device__ __forceinline__ cx<T> dot(const mom<T>& k, const W& b) {
+  return as_cx<T>(((k.k[0] * comp<0>(b) - k.k[1] * comp<1>(b)) - k.k[2] * comp<2>(b)) - k.k[3] * comp<3>(b));
 }
 
 // ------------------------------------------------------- external states
@@ -136,7 +193,7 @@ template <class T> __device__ __forceinline__ wf<T> bar(const wf<T>& s) {
 // Massless vector polarisation eps(k,lam) = (-lam e1 - i e2)/sqrt2,
 // e1 = (0, cos th cos ph, cos th sin ph, -sin th), e2 = (0, -sin ph, cos ph, 0);
 // phi = 0 on the z axis.  conj_out selects eps* (outgoing vectors).
-template <class T> __device__ __forceinline__ wf<T> ext_eps(const double* k, int lam, bool conj_out) {
+template <class T> __device__ __forceinline__ epsw<T> ext_eps(const double* k, int lam, bool conj_out) {
   const double pt2 = k[1] * k[1] + k[2] * k[2];
   const double pt = sqrt(pt2);
   const double kk = sqrt(pt2 + k[3] * k[3]);
@@ -146,31 +203,30 @@ template <class T> __device__ __forceinline__ wf<T> ext_eps(const double* k, int
   const double r2 = 0.70710678118654752440;
   const double l = double(lam);
   const double s = conj_out ? -1.0 : 1.0;
-  wf<T> e;
-  e.c[0] = c2<T>(0.0, 0.0);
-  e.c[1] = c2<T>(-l * cth * cph * r2, s * sph * r2);
-  e.c[2] = c2<T>(-l * cth * sph * r2, -s * cph * r2);
-  e.c[3] = c2<T>(l * sth * r2, 0.0);
+  epsw<T> e;
+  e.c1 = c2<T>(-l * cth * cph * r2, s * sph * r2);
+  e.c2 = c2<T>(-l * cth * sph * r2, -s * cph * r2);
+  e.c3 = T(l * sth * r2);
   return e;
 }
 
 // --------------------------------------------------- fermion-vector vertex
 // Components of J.sigma = [[b, -d], [-c, a]] and J.sigmabar = [[a, d], [c, b]],
 // a = J0+J3, b = J0-J3, c = J1 + i J2, d = J1 - i J2.
-template <class T> struct jsig { cx<T> a, b, c, d; };
-template <class T> __device__ __forceinline__ jsig<T> sig(const wf<T>& J) {
-  jsig<T> s;
-  s.a = J.c[0] + J.c[3];
-  s.b = J.c[0] - J.c[3];
-  s.c = J.c[1] + mul_i(J.c[2]);
-  s.d = J.c[1] - mul_i(J.c[2]);
-  return s;
+// For an external vector (epsw) a and b are real.
+template <class A, class B, class C, class D> struct jsig { A a; B b; C c; D d; };
+template <class W> __device__ __forceinline__ auto sig(const W& J) {
+  const auto a = comp<0>(J) + comp<3>(J);
+  const auto b = comp<0>(J) - comp<3>(J);
+  const auto c = comp<1>(J) + mul_i(comp<2>(J));
+  const auto d = comp<1>(J) - mul_i(comp<2>(J));
+  return jsig<decltype(a), decltype(b), decltype(c), decltype(d)>{a, b, c, d};
 }
 
 // Amplitude  rbar [i gamma.J (gL P_L + gR P_R)] psi.
-template <class T>
-__device__ __forceinline__ cx<T> ffv_amp(const wf<T>& r, const wf<T>& J, const wf<T>& s, T gL, T gR) {
-  const jsig<T> q = sig(J);
+template <class T, class W>
+__device__ __forceinline__ cx<T> ffv_amp(const wf<T>& r, const W& J, const wf<T>& s, T gL, T gR) {
+  const auto q = sig(J);
   // r_L (J.sigma) psi_R
   cx<T> x = r.c[0] * (q.b * s.c[2] - q.d * s.c[3]) + r.c[1] * (q.a * s.c[3] - q.c * s.c[2]);
   // r_R (J.sigmabar) psi_L
@@ -182,9 +238,9 @@ __device__ __forceinline__ cx<T> ffv_amp(const wf<T>& r, const wf<T>& J, const w
 // (or a vector and a column spinor):
 //   row  s = rbar gamma.J (gL P_L + gR P_R),   column  x = gamma.J (gL P_L + gR P_R) psi,
 // and the amplitude  i (row . column).
-template <class T>
-__device__ __forceinline__ wf<T> ffv_half_row(const wf<T>& r, const wf<T>& J, T gL, T gR) {
-  const jsig<T> q = sig(J);
+template <class T, class W>
+__device__ __forceinline__ wf<T> ffv_half_row(const wf<T>& r, const W& J, T gL, T gR) {
+  const auto q = sig(J);
   wf<T> o;
   o.c[0] = gL * (r.c[2] * q.a + r.c[3] * q.c);
   o.c[1] = gL * (r.c[2] * q.d + r.c[3] * q.b);
@@ -192,9 +248,9 @@ __device__ __forceinline__ wf<T> ffv_half_row(const wf<T>& r, const wf<T>& J, T 
   o.c[3] = gR * (r.c[1] * q.a - r.c[0] * q.d);
   return o;
 }
-template <class T>
-__device__ __forceinline__ wf<T> ffv_half_col(const wf<T>& J, const wf<T>& s, T gL, T gR) {
-  const jsig<T> q = sig(J);
+template <class T, class W>
+__device__ __forceinline__ wf<T> ffv_half_col(const W& J, const wf<T>& s, T gL, T gR) {
+  const auto q = sig(J);
   wf<T> o;
   o.c[0] = gR * (q.b * s.c[2] - q.d * s.c[3]);
   o.c[1] = gR * (q.a * s.c[3] - q.c * s.c[2]);
@@ -212,10 +268,11 @@ template <class T> __device__ __forceinline__ cx<T> amp_dot(const wf<T>& r, cons
 
 // Off-shell column spinor  i(K/+m)/(K^2-m^2+i m G) [i gamma.J (gL P_L+gR P_R)] psi.
 // K: momentum along the arrow (into the next vertex); den = 1/(K^2-m^2+i m G).
-template <class T>
-__device__ __forceinline__ wf<T> ffv_fin(const wf<T>& s, const wf<T>& J, const mom<T>& K, T m, cx<T> den,
+// m is a T, or zero_t for a massless line.
+template <class T, class W, class M>
+__device__ __forceinline__ wf<T> ffv_fin(const wf<T>& s, const W& J, const mom<T>& K, M m, cx<T> den,
                                          T gL, T gR) {
-  const jsig<T> q = sig(J);
+  const auto q = sig(J);
   const cx<T> x0 = gR * (q.b * s.c[2] - q.d * s.c[3]);
   const cx<T> x1 = gR * (q.a * s.c[3] - q.c * s.c[2]);
   const cx<T> x2 = gL * (q.a * s.c[0] + q.d * s.c[1]);
@@ -234,10 +291,10 @@ __device__ __forceinline__ wf<T> ffv_fin(const wf<T>& s, const wf<T>& J, const m
 // Off-shell row spinor  rbar [i gamma.J (gL P_L+gR P_R)] i(P/+m)/(P^2-m^2+i m G).
 // P: momentum along the arrow (= minus the momentum the row current carries
 // into its next vertex).
-template <class T>
-__device__ __forceinline__ wf<T> ffv_fout(const wf<T>& r, const wf<T>& J, const mom<T>& P, T m, cx<T> den,
+template <class T, class W, class M>
+__device__ __forceinline__ wf<T> ffv_fout(const wf<T>& r, const W& J, const mom<T>& P, M m, cx<T> den,
                                           T gL, T gR) {
-  const jsig<T> q = sig(J);
+  const auto q = sig(J);
   const cx<T> s0 = gL * (r.c[2] * q.a + r.c[3] * q.c);
   const cx<T> s1 = gL * (r.c[2] * q.d + r.c[3] * q.b);
   const cx<T> s2 = gR * (r.c[0] * q.b - r.c[1] * q.c);
@@ -295,8 +352,8 @@ __device__ __forceinline__ wf<T> ffv_vm(const wf<T>& r, const wf<T>& s, const mo
 // ---------------------------------------------------------- gluon vertices
 // V^mu(A,B) = A^mu ((k-p).B) + (A.B)(p-q)^mu + B^mu ((q-k).A) with incoming
 // momenta p = KA, q = KB and k = -(KA+KB) on the free leg.
-template <class T>
-__device__ __forceinline__ wf<T> vvv_lorentz(const wf<T>& A, const mom<T>& KA, const wf<T>& B, const mom<T>& KB) {
+template <class T, class WA, class WB>
+__device__ __forceinline__ wf<T> vvv_lorentz(const WA& A, const mom<T>& KA, const WB& B, const mom<T>& KB) {
   mom<T> kmp, pmq, qmk;
   for (int m = 0; m < 4; ++m) {
     kmp.k[m] = -T(2) * KA.k[m] - KB.k[m];
@@ -305,12 +362,15 @@ __device__ __forceinline__ wf<T> vvv_lorentz(const wf<T>& A, const mom<T>& KA, c
   }
   const cx<T> t1 = dot(kmp, B), t2 = dot(A, B), t3 = dot(qmk, A);
   wf<T> v;
-  for (int m = 0; m < 4; ++m) v.c[m] = A.c[m] * t1 + B.c[m] * t3 + pmq.k[m] * t2;
+  v.c[0] = (comp<0>(A) * t1 + comp<0>(B) * t3) + pmq.k[0] * t2;
+  v.c[1] = (comp<1>(A) * t1 + comp<1>(B) * t3) + pmq.k[1] * t2;
+  v.c[2] = (comp<2>(A) * t1 + comp<2>(B) * t3) + pmq.k[2] * t2;
+  v.c[3] = (comp<3>(A) * t1 + comp<3>(B) * t3) + pmq.k[3] * t2;
   return v;
 }
 // Off-shell gluon from a three-gluon vertex: (-i/K^2) g V^mu(A,B).
-template <class T>
-__device__ __forceinline__ wf<T> vvv_v(const wf<T>& A, const mom<T>& KA, const wf<T>& B, const mom<T>& KB,
+template <class T, class WA, class WB>
+__device__ __forceinline__ wf<T> vvv_v(const WA& A, const mom<T>& KA, const WB& B, const mom<T>& KB,
                                        T g_inv_k2) {
   wf<T> v = vvv_lorentz(A, KA, B, KB);
   for (int m = 0; m < 4; ++m) v.c[m] = mul_mi(g_inv_k2 * v.c[m]);
@@ -318,9 +378,9 @@ __device__ __forceinline__ wf<T> vvv_v(const wf<T>& A, const mom<T>& KA, const w
 }
 // Amplitude  g V^{mu nu rho}(k,p,q) X_mu A_nu B_rho with incoming momenta
 // k = KX, p = KA, q = KB (KX + KA + KB = 0).
-template <class T>
-__device__ __forceinline__ cx<T> vvv_amp(const wf<T>& X, const mom<T>& KX, const wf<T>& A, const mom<T>& KA,
-                                         const wf<T>& B, const mom<T>& KB, T g) {
+template <class T, class WX, class WA, class WB>
+__device__ __forceinline__ cx<T> vvv_amp(const WX& X, const mom<T>& KX, const WA& A, const mom<T>& KA,
+                                         const WB& B, const mom<T>& KB, T g) {
   mom<T> kmp, pmq, qmk;
   for (int m = 0; m < 4; ++m) {
     kmp.k[m] = KX.k[m] - KA.k[m];
@@ -332,11 +392,14 @@ __device__ __forceinline__ cx<T> vvv_amp(const wf<T>& X, const mom<T>& KX, const
 }
 // Four-gluon piece for the colour structure f^{x b e} f^{e c d}:
 // P^mu(b; c, d) = C^mu (B.D) - D^mu (B.C).
-template <class T>
-__device__ __forceinline__ wf<T> vvvv_piece(const wf<T>& B, const wf<T>& C, const wf<T>& D) {
+template <class T, class WB, class WC, class WD>
+__device__ __forceinline__ wf<T> vvvv_piece(const WB& B, const WC& C, const WD& D) {
   const cx<T> bd = dot(B, D), bc = dot(B, C);
   wf<T> v;
-  for (int m = 0; m < 4; ++m) v.c[m] = C.c[m] * bd - D.c[m] * bc;
+  v.c[0] = as_cx<T>(comp<0>(C) * bd - comp<0>(D) * bc);
+  v.c[1] = as_cx<T>(comp<1>(C) * bd - comp<1>(D) * bc);
+  v.c[2] = as_cx<T>(comp<2>(C) * bd - comp<2>(D) * bc);
+  v.c[3] = as_cx<T>(comp<3>(C) * bd - comp<3>(D) * bc);
   return v;
 }
 // Identity that the compiler cannot see through: a recomputed wavefunction
@@ -344,6 +407,10 @@ __device__ __forceinline__ wf<T> vvvv_piece(const wf<T>& B, const wf<T>& C, cons
 template <class T> __device__ __forceinline__ wf<T> opaque(wf<T> w) {
 #pragma unroll
   for (int m = 0; m < 4; ++m) asm volatile("" : "+v"(w.c[m].r), "+v"(w.c[m].i));
+  return w;
+}
+template <class T> __device__ __forceinline__ epsw<T> opaque(epsw<T> w) {
+  asm volatile("" : "+v"(w.c1.r), "+v"(w.c1.i), "+v"(w.c2.r), "+v"(w.c2.i), "+v"(w.c3));
   return w;
 }
 __device__ __forceinline__ double opaque_d(double x) {
