@@ -869,8 +869,8 @@ def all_programs(budget=None):
 # (budget in FP64 dwords, greedy passes) per process and arithmetic type,
 # and whether amplitudes share half contractions; chosen by measurement on
 # gfx950 (2^20 gg -> t tbar gg events)
-DEFAULT_SCHEDULE_F64 = {"eemumu": (256, 4), "ggtt": (256, 4), "ggttg": (256, 4), "ggttgg": (256, 4)}
-DEFAULT_SCHEDULE_F32 = {"eemumu": (256, 4), "ggtt": (256, 4), "ggttg": (384, 1), "ggttgg": (384, 2)}
+DEFAULT_SCHEDULE_F64 = {"eemumu": (256, 4), "ggtt": (256, 4), "ggttg": (256, 4), "ggttgg": (320, 4)}
+DEFAULT_SCHEDULE_F32 = {"eemumu": (256, 4), "ggtt": (256, 4), "ggttg": (384, 1), "ggttgg": (448, 2)}
 SHARE_HALF = {"ggttg": False, "ggttgg": False, "ggttggg": True}
 # FP64 forms that keep their jamps in LDS (frees 4 registers per colour flow
 # for the wavefunction schedule; gg -> t tbar gg FP64 91 -> 79 ms per 2^20)
