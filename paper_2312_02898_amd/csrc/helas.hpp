@@ -268,9 +268,10 @@ template <class T> __device__ __forceinline__ cx<T> amp_dot(const wf<T>& r, cons
 
 // Off-shell column spinor  i(K/+m)/(K^2-m^2+i m G) [i gamma.J (gL P_L+gR P_R)] psi.
 // K: momentum along the arrow (into the next vertex); den = 1/(K^2-m^2+i m G).
-// m is a T, or zero_t for a massless line.
-template <class T, class W, class M>
-__device__ __forceinline__ wf<T> ffv_fin(const wf<T>& s, const W& J, const mom<T>& K, M m, cx<T> den,
+// m is a T, or zero_t for a massless line; den a cx<T>, or re<T> for a
+// massless line (1/K^2).
+template <class T, class W, class M, class DN>
+__device__ __forceinline__ wf<T> ffv_fin(const wf<T>& s, const W& J, const mom<T>& K, M m, DN den,
                                          T gL, T gR) {
   const auto q = sig(J);
   const cx<T> x0 = gR * (q.b * s.c[2] - q.d * s.c[3]);
@@ -279,7 +280,7 @@ __device__ __forceinline__ wf<T> ffv_fin(const wf<T>& s, const W& J, const mom<T
   const cx<T> x3 = gL * (q.c * s.c[0] + q.b * s.c[1]);
   const T kp = K.k[0] + K.k[3], km = K.k[0] - K.k[3];
   const cx<T> kc{K.k[1], K.k[2]}, kd{K.k[1], -K.k[2]};   // K1 + i K2, K1 - i K2
-  const cx<T> nd = -den;                                 // i * i * den
+  const auto nd = -den;                                  // i * i * den
   wf<T> o;
   o.c[0] = nd * (km * x2 - kd * x3 + m * x0);
   o.c[1] = nd * (kp * x3 - kc * x2 + m * x1);
@@ -291,8 +292,8 @@ __device__ __forceinline__ wf<T> ffv_fin(const wf<T>& s, const W& J, const mom<T
 // Off-shell row spinor  rbar [i gamma.J (gL P_L+gR P_R)] i(P/+m)/(P^2-m^2+i m G).
 // P: momentum along the arrow (= minus the momentum the row current carries
 // into its next vertex).
-template <class T, class W, class M>
-__device__ __forceinline__ wf<T> ffv_fout(const wf<T>& r, const W& J, const mom<T>& P, M m, cx<T> den,
+template <class T, class W, class M, class DN>
+__device__ __forceinline__ wf<T> ffv_fout(const wf<T>& r, const W& J, const mom<T>& P, M m, DN den,
                                           T gL, T gR) {
   const auto q = sig(J);
   const cx<T> s0 = gL * (r.c[2] * q.a + r.c[3] * q.c);
@@ -301,7 +302,7 @@ __device__ __forceinline__ wf<T> ffv_fout(const wf<T>& r, const W& J, const mom<
   const cx<T> s3 = gR * (r.c[1] * q.a - r.c[0] * q.d);
   const T kp = P.k[0] + P.k[3], km = P.k[0] - P.k[3];
   const cx<T> kc{P.k[1], P.k[2]}, kd{P.k[1], -P.k[2]};
-  const cx<T> nd = -den;
+  const auto nd = -den;
   wf<T> o;
   // (s_L, s_R) [[m, P.sigma], [P.sigmabar, m]]
   o.c[0] = nd * (m * s0 + kp * s2 + kc * s3);

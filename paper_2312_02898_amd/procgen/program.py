@@ -60,14 +60,15 @@ def _zero_saving(op, eps) -> int:
     component, or because a fermion line is massless (same counting rules as
     FLOPS).  Per wavefunction-wavefunction product: 12 with one such vector,
     14 with two; per momentum-vector product: 6; per fermion-vector vertex
-    with the vector external: 20; massless fermion propagator: 16."""
+    with the vector external: 20; massless fermion propagator (zero mass,
+    real 1/K^2): 32."""
     k = op.kind
     isv = [v.split("_r")[0] in eps for v in op.ins]
 
     def wdot(a, b):
         return 14 if a and b else (12 if a or b else 0)
     if k in ("ffv_fin", "ffv_fout", "ffv_half_row", "amp_ffv"):
-        return 20 * isv[1] + (16 if k in ("ffv_fin", "ffv_fout") and op.prm.get("light") else 0)
+        return 20 * isv[1] + (32 if k in ("ffv_fin", "ffv_fout") and op.prm.get("light") else 0)
     if k == "ffv_half_col":
         return 20 * isv[0]
     if k == "vvv_v":
