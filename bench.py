@@ -40,8 +40,8 @@ MEASURED_TRAFFIC = {
 
 def kernel_digest(variant):
     """Digest of the sources that make the gg -> t t~ g g mixed kernel: its
-    generated FP32 amplitude function and colour form, the kernel and device
-    headers and the compiler flags."""
+    generated FP32 amplitude function, colour form and propagator-cache fill,
+    the kernel and device headers and the compiler flags."""
     import hashlib
     from paper_2312_02898_amd import build as pb
     csrc = os.path.join(ROOT, "paper_2312_02898_amd", "csrc")
@@ -51,13 +51,14 @@ def kernel_digest(variant):
     b = inc.index("\n  }\n", a)
     h = hashlib.sha256(inc[a:b].encode())
     if variant == "valu":
-        a = inc.index("static T colour_sum")
-        h.update(inc[a:inc.index("\n  }\n", a)].encode())
+        for fn in ("static T colour_sum", "static void den_fill_f32"):
+            a = inc.index(fn)
+            h.update(inc[a:inc.index("\n  }\n", a)].encode())
     # the kernel template itself (not the rest of kernels.hpp: dispatch code
     # does not change the kernel's binary)
     with open(os.path.join(csrc, "kernels.hpp")) as fh:
         kh = fh.read()
-    name = "void me_kernel(" if variant == "valu" else "void me_kernel_mfma("
+    name = "void me_kernel_kc(" if variant == "valu" else "void me_kernel_mfma("
     a = kh.rindex("template", 0, kh.index(name))
     h.update(kh[a:kh.index("\n}\n", a)].encode())
     files = ("helas.hpp", "me_types.h") + (("colour_mfma.hpp",) if variant != "valu" else ())
@@ -175,7 +176,7 @@ def main():
     variants = {"mfma_f16_hilo": {"ME_s": args.nevt * args.steps / wall_m, "kernel_ms": k_m / args.steps * 1e3,
                                   "kernel": "me_kernel_mfma<Proc_ggttgg, false>"},
                 "valu": {"ME_s": args.nevt * args.steps / wall_v, "kernel_ms": k_v / args.steps * 1e3,
-                         "kernel": "me_kernel<Proc_ggttgg, float>"}}
+                         "kernel": "me_kernel_kc<Proc_ggttgg>"}}
     best = "valu" if wall_v < wall_m else "mfma_f16_hilo"
     if best == "valu":
         wall32, k32, me32 = wall_v, k_v, me_valu

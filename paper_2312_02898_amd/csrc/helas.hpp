@@ -193,7 +193,11 @@ template <class T> __device__ __forceinline__ wf<T> bar(const wf<T>& s) {
 // Massless vector polarisation eps(k,lam) = (-lam e1 - i e2)/sqrt2,
 // e1 = (0, cos th cos ph, cos th sin ph, -sin th), e2 = (0, -sin ph, cos ph, 0);
 // phi = 0 on the z axis.  conj_out selects eps* (outgoing vectors).
-template <class T> __device__ __forceinline__ epsw<T> ext_eps(const double* k, int lam, bool conj_out) {
+// The helicity enters only as a sign: with a = (cth cph, cth sph, sth)/sqrt2
+// and b = (sph, -cph)/sqrt2 (eps_base), eps = (0, -lam a0 + i s b0,
+// -lam a1 + i s b1, lam a2) with s = -1 for eps*, +1 otherwise.
+struct EpsBase { double a0, a1, a2, b0, b1; };
+__device__ __forceinline__ EpsBase eps_base(const double* k) {
   const double pt2 = k[1] * k[1] + k[2] * k[2];
   const double pt = sqrt(pt2);
   const double kk = sqrt(pt2 + k[3] * k[3]);
@@ -201,13 +205,21 @@ template <class T> __device__ __forceinline__ epsw<T> ext_eps(const double* k, i
   if (pt > 0) { cph = k[1] / pt; sph = k[2] / pt; cth = k[3] / kk; sth = pt / kk; }
   else { cth = k[3] >= 0 ? 1.0 : -1.0; sth = 0.0; }
   const double r2 = 0.70710678118654752440;
-  const double l = double(lam);
-  const double s = conj_out ? -1.0 : 1.0;
+  return EpsBase{cth * cph * r2, cth * sph * r2, sth * r2, sph * r2, -cph * r2};
+}
+// eps from its base values (already rounded to T): only sign changes.
+template <class T> __device__ __forceinline__ epsw<T> eps_from_base(T a0, T a1, T a2, T b0, T b1, int lam,
+                                                                    bool conj_out) {
   epsw<T> e;
-  e.c1 = c2<T>(-l * cth * cph * r2, s * sph * r2);
-  e.c2 = c2<T>(-l * cth * sph * r2, -s * cph * r2);
-  e.c3 = T(l * sth * r2);
+  const T l = T(lam), s = conj_out ? T(-1) : T(1);
+  e.c1 = cx<T>{-l * a0, s * b0};
+  e.c2 = cx<T>{-l * a1, s * b1};
+  e.c3 = l * a2;
   return e;
+}
+template <class T> __device__ __forceinline__ epsw<T> ext_eps(const double* k, int lam, bool conj_out) {
+  const EpsBase b = eps_base(k);
+  return eps_from_base<T>(T(b.a0), T(b.a1), T(b.a2), T(b.b0), T(b.b1), lam, conj_out);
 }
 
 // --------------------------------------------------- fermion-vector vertex
@@ -427,6 +439,13 @@ template <class T> __device__ __forceinline__ void hold(cx<T>& a) {
 template <class T, int N> __device__ __forceinline__ void hold_jamp(cx<T> (&jamp)[N], int k) { hold(jamp[k]); }
 // jamps kept in memory are not sunk
 template <class J> __device__ __forceinline__ void hold_jamp(J&, int) {}
+
+// Per-event cache of propagator factors: the generated FP32 amplitude
+// function reads them from the cache when the kernel passes one (kCached) and
+// forms them in place from the momenta otherwise (this type).
+struct NoKinCache {
+  static constexpr bool kCached = false;
+};
 
 // A momentum copy the compiler cannot identify with the original, for
 // recomputed external wavefunctions (which have no wavefunction input).

@@ -60,6 +60,88 @@ __global__ __launch_bounds__(256) void me_kernel(const double* __restrict__ mom,
   if (out) out[e] = acc * (P::coupling_factor(prm) / (P::CDEN * P::IDEN));
 }
 
+// Propagator factors and polarisation bases (eps_base) of one event in LDS,
+// formed once per event before the helicity loop (they do not depend on the
+// helicity): slot s of thread t at base[s * 256 + t], so a wave's 64 reads of
+// one slot are contiguous; a polarisation base takes five slots.  The
+// per-iteration offset passes through an empty asm statement, so the reads
+// stay inside the helicity loop where the schedule put them instead of being
+// hoisted out of it and held in registers across the loop.
+template <class T>
+struct LdsKinCache {
+  static constexpr bool kCached = true;
+  T* re;
+  cx<T>* cxs;
+  T* eb;
+  int off;
+  __device__ __forceinline__ T r(int s) const { return re[s * 256 + off]; }
+  __device__ __forceinline__ cx<T> c(int s) const { return cxs[s * 256 + off]; }
+  __device__ __forceinline__ T r_opq(int s) const {
+    int o = off;
+    asm volatile("" : "+v"(o));
+    return re[s * 256 + o];
+  }
+  __device__ __forceinline__ cx<T> c_opq(int s) const {
+    int o = off;
+    asm volatile("" : "+v"(o));
+    return cxs[s * 256 + o];
+  }
+  __device__ __forceinline__ epsw<T> eps_at(int j, int o, int lam, bool conj_out) const {
+    const T* b = eb + 5 * j * 256 + o;
+    return eps_from_base<T>(b[0], b[256], b[512], b[768], b[1024], lam, conj_out);
+  }
+  __device__ __forceinline__ epsw<T> eps(int j, int lam, bool conj_out) const { return eps_at(j, off, lam, conj_out); }
+  __device__ __forceinline__ epsw<T> eps_opq(int j, int lam, bool conj_out) const {
+    int o = off;
+    asm volatile("" : "+v"(o));
+    return eps_at(j, o, lam, conj_out);
+  }
+  __device__ __forceinline__ void set_eps(int j, T a0, T a1, T a2, T b0, T b1) {
+    T* b = eb + 5 * j * 256 + off;
+    b[0] = a0; b[256] = a1; b[512] = a2; b[768] = b0; b[1024] = b1;
+  }
+  __device__ __forceinline__ void set_r(int s, T v) { re[s * 256 + off] = v; }
+  __device__ __forceinline__ void set_c(int s, cx<T> v) { cxs[s * 256 + off] = v; }
+};
+
+// Mixed form with the vector-ALU colour sum and the kinematic cache in LDS
+// (256-thread blocks; per thread P::KC_RE_F32 real and P::KC_CX_F32 complex
+// propagator-factor slots and P::KC_EPS_F32 polarisation bases).
+template <class P>
+__global__ __launch_bounds__(256) void me_kernel_kc(const double* __restrict__ mom, int64_t nevt,
+                                                    double* __restrict__ out, const MeParams prm) {
+  constexpr int NR = P::KC_RE_F32 > 0 ? P::KC_RE_F32 : 1;
+  constexpr int NC = P::KC_CX_F32 > 0 ? P::KC_CX_F32 : 1;
+  constexpr int NE = P::KC_EPS_F32 > 0 ? P::KC_EPS_F32 : 1;
+  __shared__ float kre[NR * 256];
+  __shared__ cx<float> kcx[NC * 256];
+  __shared__ float keps[5 * NE * 256];
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= nevt) return;
+  double p[P::NPAR][4];
+  const double2* src = reinterpret_cast<const double2*>(mom + e * (4 * P::NPAR));
+#pragma unroll
+  for (int i = 0; i < P::NPAR; ++i) {
+    const double2 a = src[2 * i], b = src[2 * i + 1];
+    p[i][0] = a.x; p[i][1] = a.y; p[i][2] = b.x; p[i][3] = b.y;
+  }
+  LdsKinCache<float> dc{kre, kcx, keps, int(threadIdx.x)};
+  P::template den_fill_f32<float>(p, prm, dc);
+  double acc = 0.0;
+  for (int ih = 0; ih < prm.nhel; ++ih) {
+#pragma unroll
+    for (int i = 0; i < P::NPAR; ++i)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) asm volatile("" : "+v"(p[i][c]));
+    asm volatile("" : "+v"(dc.off));
+    const unsigned hel = prm.hel[ih];
+    cx<float> jamp[P::NCOLOR];
+    P::template amplitudes<float>(p, hel, prm, jamp, dc);
+    acc += double(P::template colour_sum<float>(jamp));
+  }
+  if (out) out[e] = acc * (P::coupling_factor(prm) / (P::CDEN * P::IDEN));
+}
+
 // Jamps of one lane held in LDS instead of registers: element k of lane l at
 // base[k * 64 + l], so a wave's 64 accesses to one jamp are contiguous.
 template <class T>
@@ -180,6 +262,8 @@ int launch(int mode, const double* mom, int64_t nevt, double* out, double* out_h
       const int64_t nb = (nevt + 127) / 128;
       hipLaunchKernelGGL((me_kernel_ldsjamp<P, float>), dim3(unsigned(nb)), dim3(128), 0, stream, mom, nevt,
                          out, nullptr, prm);
+    } else if constexpr (P::KC_RE_F32 + P::KC_CX_F32 > 0) {
+      hipLaunchKernelGGL((me_kernel_kc<P>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out, prm);
     } else {
       hipLaunchKernelGGL((me_kernel<P, float>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
                          nullptr, prm);

@@ -5,7 +5,8 @@ the device functions they call (``csrc/helas.hpp``) are plain C++ apart from
 HIP qualifiers and empty ``asm`` barriers.  Compiled with g++ behind a small
 shim (qualifiers defined away, barriers dropped), they evaluate |M|^2 on the
 CPU: the jamps of every helicity (FP64 and FP32 schedules) and the colour
-sum with the integer colour matrix.  This pins the diagram enumeration, colour decomposition, schedule
+sum with the integer colour matrix; an FP32 form whose kernel caches its
+propagator factors per event runs through a host stand-in of that cache.  This pins the diagram enumeration, colour decomposition, schedule
 (recomputation, evictions, jamp write-backs of the split form) and code
 emission against the oracle without a GPU.  The GPU kernels themselves are
 covered by the ``gpu`` tests.
@@ -64,6 +65,22 @@ template <int J, class Q = P> void parts(const double (&p)[P::NPAR][4], unsigned
   static cx<T> qb[NQ > 0 ? NQ : 1];
   if constexpr (J < N) { Q::template part<T, J>(p, h, prm, X, 1, qb); parts<J + 1, Q>(p, h, prm, X); }
 }
+// stands in for the kernel's per-event LDS cache of propagator factors
+template <class T> struct HostKinCache {
+  static constexpr bool kCached = true;
+  T re[64];
+  cx<T> cxs[64];
+  T r(int s) const { return re[s]; }
+  cx<T> c(int s) const { return cxs[s]; }
+  T r_opq(int s) const { return re[s]; }
+  cx<T> c_opq(int s) const { return cxs[s]; }
+  void set_r(int s, T v) { re[s] = v; }
+  void set_c(int s, cx<T> v) { cxs[s] = v; }
+  T eb[16][5];
+  epsw<T> eps(int j, int lam, bool cj) const { return eps_from_base<T>(eb[j][0], eb[j][1], eb[j][2], eb[j][3], eb[j][4], lam, cj); }
+  epsw<T> eps_opq(int j, int lam, bool cj) const { return eps(j, lam, cj); }
+  void set_eps(int j, T a0, T a1, T a2, T b0, T b1) { eb[j][0] = a0; eb[j][1] = a1; eb[j][2] = a2; eb[j][3] = b0; eb[j][4] = b1; }
+};
 // a template, so that the branch for the other form is discarded
 template <class Q>
 void jamps(const double (&p)[Q::NPAR][4], unsigned h, const MeParams& prm, cx<T>* J) {
@@ -72,6 +89,13 @@ void jamps(const double (&p)[Q::NPAR][4], unsigned h, const MeParams& prm, cx<T>
     parts<0>(p, h, prm, J);
   } else if constexpr (sizeof(T) == 8) {
     Q::template amplitudes_f64<T>(p, h, prm, J);
+  } else if constexpr (Q::KC_RE_F32 + Q::KC_CX_F32 > 0) {
+    static_assert(Q::KC_RE_F32 <= 64 && Q::KC_CX_F32 <= 64 && Q::KC_EPS_F32 <= 16, "host cache too small");
+    HostKinCache<T> dc;
+    for (int s = 0; s < 64; ++s) { dc.re[s] = T(1e30); dc.cxs[s] = cx<T>{T(1e30), T(1e30)}; }
+    for (int s = 0; s < 16; ++s) for (int c = 0; c < 5; ++c) dc.eb[s][c] = T(1e30);
+    Q::template den_fill_f32<T>(p, prm, dc);
+    Q::template amplitudes_f32<T>(p, h, prm, J, dc);
   } else {
     Q::template amplitudes_f32<T>(p, h, prm, J);
   }
