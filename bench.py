@@ -176,7 +176,7 @@ def main():
     variants = {"mfma_f16_hilo": {"ME_s": args.nevt * args.steps / wall_m, "kernel_ms": k_m / args.steps * 1e3,
                                   "kernel": "me_kernel_mfma<Proc_ggttgg, false>"},
                 "valu": {"ME_s": args.nevt * args.steps / wall_v, "kernel_ms": k_v / args.steps * 1e3,
-                         "kernel": "me_kernel_kc<Proc_ggttgg>"}}
+                         "kernel": "me_kernel_kc<Proc_ggttgg, float>"}}
     best = "valu" if wall_v < wall_m else "mfma_f16_hilo"
     if best == "valu":
         wall32, k32, me32 = wall_v, k_v, me_valu

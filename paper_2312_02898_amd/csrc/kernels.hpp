@@ -104,18 +104,21 @@ struct LdsKinCache {
   __device__ __forceinline__ void set_c(int s, cx<T> v) { cxs[s * 256 + off] = v; }
 };
 
-// Mixed form with the vector-ALU colour sum and the kinematic cache in LDS
-// (256-thread blocks; per thread P::KC_RE_F32 real and P::KC_CX_F32 complex
-// propagator-factor slots and P::KC_EPS_F32 polarisation bases).
-template <class P>
+// The kinematic cache in LDS with the vector-ALU colour sum (256-thread
+// blocks; per thread KC_RE real and KC_CX complex propagator-factor slots and
+// KC_EPS polarisation bases of the form's schedule).  T = float: mixed form
+// (out_hel unused); T = double: FP64 form (out_hel as in me_kernel).
+template <class P, class T>
 __global__ __launch_bounds__(256) void me_kernel_kc(const double* __restrict__ mom, int64_t nevt,
-                                                    double* __restrict__ out, const MeParams prm) {
-  constexpr int NR = P::KC_RE_F32 > 0 ? P::KC_RE_F32 : 1;
-  constexpr int NC = P::KC_CX_F32 > 0 ? P::KC_CX_F32 : 1;
-  constexpr int NE = P::KC_EPS_F32 > 0 ? P::KC_EPS_F32 : 1;
-  __shared__ float kre[NR * 256];
-  __shared__ cx<float> kcx[NC * 256];
-  __shared__ float keps[5 * NE * 256];
+                                                    double* __restrict__ out, double* __restrict__ out_hel,
+                                                    const MeParams prm) {
+  constexpr bool F64 = sizeof(T) == 8;
+  constexpr int KR = F64 ? P::KC_RE_F64 : P::KC_RE_F32;
+  constexpr int KC = F64 ? P::KC_CX_F64 : P::KC_CX_F32;
+  constexpr int KE = F64 ? P::KC_EPS_F64 : P::KC_EPS_F32;
+  __shared__ T kre[(KR > 0 ? KR : 1) * 256];
+  __shared__ cx<T> kcx[(KC > 0 ? KC : 1) * 256];
+  __shared__ T keps[5 * (KE > 0 ? KE : 1) * 256];
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= nevt) return;
   double p[P::NPAR][4];
@@ -125,8 +128,9 @@ __global__ __launch_bounds__(256) void me_kernel_kc(const double* __restrict__ m
     const double2 a = src[2 * i], b = src[2 * i + 1];
     p[i][0] = a.x; p[i][1] = a.y; p[i][2] = b.x; p[i][3] = b.y;
   }
-  LdsKinCache<float> dc{kre, kcx, keps, int(threadIdx.x)};
-  P::template den_fill_f32<float>(p, prm, dc);
+  LdsKinCache<T> dc{kre, kcx, keps, int(threadIdx.x)};
+  if constexpr (F64) P::template den_fill_f64<T>(p, prm, dc);
+  else P::template den_fill_f32<T>(p, prm, dc);
   double acc = 0.0;
   for (int ih = 0; ih < prm.nhel; ++ih) {
 #pragma unroll
@@ -135,9 +139,13 @@ __global__ __launch_bounds__(256) void me_kernel_kc(const double* __restrict__ m
       for (int c = 0; c < 4; ++c) asm volatile("" : "+v"(p[i][c]));
     asm volatile("" : "+v"(dc.off));
     const unsigned hel = prm.hel[ih];
-    cx<float> jamp[P::NCOLOR];
-    P::template amplitudes<float>(p, hel, prm, jamp, dc);
-    acc += double(P::template colour_sum<float>(jamp));
+    cx<T> jamp[P::NCOLOR];
+    P::template amplitudes<T>(p, hel, prm, jamp, dc);
+    const double q = double(P::template colour_sum<T>(jamp));
+    if constexpr (F64) {
+      if (out_hel) out_hel[e * P::NHEL + hel] = q * (P::coupling_factor(prm) / P::CDEN);
+    }
+    acc += q;
   }
   if (out) out[e] = acc * (P::coupling_factor(prm) / (P::CDEN * P::IDEN));
 }
@@ -242,6 +250,9 @@ int launch(int mode, const double* mom, int64_t nevt, double* out, double* out_h
       const int64_t nb = (nevt + 127) / 128;
       hipLaunchKernelGGL((me_kernel_ldsjamp<P, double>), dim3(unsigned(nb)), dim3(128), 0, stream, mom, nevt,
                          out, out_hel, prm);
+    } else if constexpr (P::KC_RE_F64 + P::KC_CX_F64 + P::KC_EPS_F64 > 0) {
+      hipLaunchKernelGGL((me_kernel_kc<P, double>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
+                         out_hel, prm);
     } else {
       hipLaunchKernelGGL((me_kernel<P, double>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
                          out_hel, prm);
@@ -262,8 +273,9 @@ int launch(int mode, const double* mom, int64_t nevt, double* out, double* out_h
       const int64_t nb = (nevt + 127) / 128;
       hipLaunchKernelGGL((me_kernel_ldsjamp<P, float>), dim3(unsigned(nb)), dim3(128), 0, stream, mom, nevt,
                          out, nullptr, prm);
-    } else if constexpr (P::KC_RE_F32 + P::KC_CX_F32 > 0) {
-      hipLaunchKernelGGL((me_kernel_kc<P>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out, prm);
+    } else if constexpr (P::KC_RE_F32 + P::KC_CX_F32 + P::KC_EPS_F32 > 0) {
+      hipLaunchKernelGGL((me_kernel_kc<P, float>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
+                         nullptr, prm);
     } else {
       hipLaunchKernelGGL((me_kernel<P, float>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
                          nullptr, prm);

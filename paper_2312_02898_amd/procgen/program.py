@@ -859,6 +859,7 @@ def all_programs(budget=None):
         p.f32_lds_jamps = p.name in F32_LDS_JAMPS
         p.mixed_mfma = p.name in MIXED_MFMA
         p.den_cache_f32 = p.name in DEN_CACHE_F32
+        p.den_cache_f64 = p.name in DEN_CACHE_F64 and not p.fp64_lds_jamps
         b64, i64 = DEFAULT_SCHEDULE_F64.get(p.name, (256, 4))
         b32, i32 = DEFAULT_SCHEDULE_F32.get(p.name, (512, 4))
         schedule(p, budget if budget is not None else b32, i32)
@@ -881,7 +882,11 @@ FP64_LDS_JAMPS = {"ggttgg"}
 F32_LDS_JAMPS = set()
 # mixed forms whose vector-ALU kernel forms the propagator factors once per
 # event into LDS instead of once per helicity
-DEN_CACHE_F32 = {"ggttgg"}
+DEN_CACHE_F32 = {"eemumu", "ggtt", "ggttg", "ggttgg", "uutt", "uxutt", "uuttg", "uxuttg", "ugttu", "guttu",
+                 "uxgttux", "guxttux"}
+# the same for FP64 forms whose jamps stay in registers
+DEN_CACHE_F64 = {"eemumu", "ggtt", "ggttg", "uutt", "uxutt", "uuttg", "uxuttg", "ugttu", "guttu", "uxgttux",
+                 "guxttux"}
 # processes whose default mixed form (ME_MIXED) sums colours on FP16 hi+lo
 # MFMA; the others use the vector ALU (chosen by measurement)
 MIXED_MFMA = set()

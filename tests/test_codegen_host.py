@@ -5,8 +5,9 @@ the device functions they call (``csrc/helas.hpp``) are plain C++ apart from
 HIP qualifiers and empty ``asm`` barriers.  Compiled with g++ behind a small
 shim (qualifiers defined away, barriers dropped), they evaluate |M|^2 on the
 CPU: the jamps of every helicity (FP64 and FP32 schedules) and the colour
-sum with the integer colour matrix; an FP32 form whose kernel caches its
-propagator factors per event runs through a host stand-in of that cache.  This pins the diagram enumeration, colour decomposition, schedule
+sum with the integer colour matrix; a form whose kernel caches its
+propagator factors and polarisation bases per event runs through a host
+stand-in of that cache.  This pins the diagram enumeration, colour decomposition, schedule
 (recomputation, evictions, jamp write-backs of the split form) and code
 emission against the oracle without a GPU.  The GPU kernels themselves are
 covered by the ``gpu`` tests.
@@ -87,9 +88,16 @@ void jamps(const double (&p)[Q::NPAR][4], unsigned h, const MeParams& prm, cx<T>
   if constexpr (Q::SPLIT) {
     for (int k = 0; k < Q::NCOLOR; ++k) J[k] = cx<T>{T(1e30), T(1e30)};   // every jamp must be stored
     parts<0>(p, h, prm, J);
+  } else if constexpr (sizeof(T) == 8 && Q::KC_RE_F64 + Q::KC_CX_F64 + Q::KC_EPS_F64 > 0) {
+    static_assert(Q::KC_RE_F64 <= 64 && Q::KC_CX_F64 <= 64 && Q::KC_EPS_F64 <= 16, "host cache too small");
+    HostKinCache<T> dc;
+    for (int s = 0; s < 64; ++s) { dc.re[s] = T(1e30); dc.cxs[s] = cx<T>{T(1e30), T(1e30)}; }
+    for (int s = 0; s < 16; ++s) for (int c = 0; c < 5; ++c) dc.eb[s][c] = T(1e30);
+    Q::template den_fill_f64<T>(p, prm, dc);
+    Q::template amplitudes_f64<T>(p, h, prm, J, dc);
   } else if constexpr (sizeof(T) == 8) {
     Q::template amplitudes_f64<T>(p, h, prm, J);
-  } else if constexpr (Q::KC_RE_F32 + Q::KC_CX_F32 > 0) {
+  } else if constexpr (Q::KC_RE_F32 + Q::KC_CX_F32 + Q::KC_EPS_F32 > 0) {
     static_assert(Q::KC_RE_F32 <= 64 && Q::KC_CX_F32 <= 64 && Q::KC_EPS_F32 <= 16, "host cache too small");
     HostKinCache<T> dc;
     for (int s = 0; s < 64; ++s) { dc.re[s] = T(1e30); dc.cxs[s] = cx<T>{T(1e30), T(1e30)}; }
