@@ -33,8 +33,8 @@ FP64_VECTOR_PEAK = 78.6e12    # MI355X fp64 vector FLOP/s
 # the kernel source they were taken on (digest below); null otherwise.
 PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 MEASURED_TRAFFIC = {
-    "valu": {"digest": "5c6864861f074510", "fetch_kib": 99034, "write_kib": 8192},
-    "mfma_f16_hilo": {"digest": "e29b5c956a83b294", "fetch_kib": 99018, "write_kib": 8192},
+    "valu": {"digest": "f2e9ba516e7a9fbd", "fetch_kib": 99034, "write_kib": 8192},
+    "mfma_f16_hilo": {"digest": "e29b5c956a83b294", "fetch_kib": 99014, "write_kib": 8192},
 }
 
 
