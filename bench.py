@@ -128,7 +128,7 @@ def main():
     ap.add_argument("--nevt", type=int, default=1 << 20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serving-requests", type=int, default=400)
+    ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--ggttggg-nevt", type=int, default=1 << 20)
     ap.add_argument("--channels-nevt", type=int, default=1 << 20)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
