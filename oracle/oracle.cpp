@@ -312,7 +312,7 @@ QqgLegs qqg_legs(int proc) {
 // Diagram-basis colour factors for explicit colours (r, c of the light line's
 // row and column ends, t, tb of the top line's, b of the gluon) and the 5x5
 // matrix sum_colours conj(c_D) c_D', by brute force.
-const std::vector<std::complex<double>>& qqg_colour_matrix();
+const std::vector<std::complex<long double>>& qqg_colour_matrix();
 
 template <class T> M4<T> m4_scale(const M4<T>& a, cx<T> s) {
   M4<T> r;
@@ -418,7 +418,7 @@ template <class T> T qqg_me_hel(const Couplings<T>& c, const T (*p)[4], int proc
   T sum = 0;
   for (int d = 0; d < 5; ++d)
     for (int e = 0; e < 5; ++e) {
-      const std::complex<double> cde = C[size_t(d) * 5 + e];
+      const std::complex<long double> cde = C[size_t(d) * 5 + e];
       sum += (std::conj(A[d]) * cx<T>(T(cde.real()), T(cde.imag())) * A[e]).real();
     }
   return sum;
@@ -560,11 +560,15 @@ void partial_amps(const Couplings<T>& c, const QcdEvent<T>& ev, cx<T>* A) {
 }
 
 // --------------------------------------------------------------- SU(3)
-struct SU3 {
-  std::complex<double> t[8][3][3];
-  double f[8][8][8];
-  SU3() {
-    typedef std::complex<double> C;
+// R is the real type of the entries: double for the colour-dressed pins,
+// long double for the colour matrices, whose rounding would otherwise bound
+// the long-double evaluation's accuracy on events where the colour sum
+// cancels strongly.
+template <class R> struct SU3T {
+  std::complex<R> t[8][3][3];
+  R f[8][8][8];
+  SU3T() {
+    typedef std::complex<R> C;
     const C I(0, 1);
     for (int a = 0; a < 8; ++a)
       for (int i = 0; i < 3; ++i)
@@ -576,11 +580,11 @@ struct SU3 {
     t[4][0][2] = -I; t[4][2][0] = I;
     t[5][1][2] = t[5][2][1] = 1;
     t[6][1][2] = -I; t[6][2][1] = I;
-    double r3 = 1.0 / std::sqrt(3.0);
+    const R r3 = R(1) / std::sqrt(R(3));
     t[7][0][0] = r3; t[7][1][1] = r3; t[7][2][2] = -2 * r3;
     for (int a = 0; a < 8; ++a)
       for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) t[a][i][j] *= 0.5;
+        for (int j = 0; j < 3; ++j) t[a][i][j] *= R(0.5);
     // f^{abc} = -2 i Tr(t^a [t^b, t^c])
     for (int a = 0; a < 8; ++a)
       for (int b = 0; b < 8; ++b)
@@ -590,12 +594,14 @@ struct SU3 {
             for (int j = 0; j < 3; ++j)
               for (int k = 0; k < 3; ++k)
                 tr += t[a][i][j] * (t[b][j][k] * t[c][k][i] - t[c][j][k] * t[b][k][i]);
-          double v = (-2.0 * I * tr).real();
-          f[a][b][c] = std::fabs(v) < 1e-14 ? 0.0 : v;
+          R v = (R(-2) * I * tr).real();
+          f[a][b][c] = std::fabs(v) < R(1e-14) ? R(0) : v;
         }
   }
 };
+using SU3 = SU3T<double>;
 const SU3& su3() { static const SU3 s; return s; }
+const SU3T<long double>& su3l() { static const SU3T<long double> s; return s; }
 
 // c_sigma for explicit colours.
 void colour_basis_values(int n, const int* col, std::complex<double>* out) {
@@ -618,8 +624,8 @@ void colour_basis_values(int n, const int* col, std::complex<double>* out) {
 }
 
 // C[sigma][tau] = sum_{a_1..a_n} Tr(P_sigma^dagger P_tau), P = t^{a_s1}...t^{a_sn}.
-std::vector<double> colour_matrix_brute(int n) {
-  const SU3& s = su3();
+std::vector<long double> colour_matrix_brute(int n) {
+  const SU3T<long double>& s = su3l();
   const int nf = int(factorial(n));
   long nassign = 1;
   for (int i = 0; i < n; ++i) nassign *= 8;
@@ -629,21 +635,21 @@ std::vector<double> colour_matrix_brute(int n) {
     for (int i = 0; i < n; ++i) p[i] = i;
     do perms.push_back(p); while (std::next_permutation(p.begin(), p.end()));
   }
-  std::vector<std::complex<double>> C(size_t(nf) * nf, 0.0);
+  std::vector<std::complex<long double>> C(size_t(nf) * nf, 0.0);
   std::mutex mtx;
 #pragma omp parallel
   {
-    std::vector<std::complex<double>> Cl(size_t(nf) * nf, 0.0);
-    std::vector<std::complex<double>> P(size_t(nf) * 9);
+    std::vector<std::complex<long double>> Cl(size_t(nf) * nf, 0.0);
+    std::vector<std::complex<long double>> P(size_t(nf) * 9);
 #pragma omp for schedule(dynamic)
     for (long as = 0; as < nassign; ++as) {
       int a[5];
       long r = as;
       for (int i = 0; i < n; ++i) { a[i] = int(r % 8); r /= 8; }
       for (int si = 0; si < nf; ++si) {
-        std::complex<double> M[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+        std::complex<long double> M[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
         for (int l = 0; l < n; ++l) {
-          std::complex<double> N[3][3];
+          std::complex<long double> N[3][3];
           const auto& tm = s.t[a[perms[si][l]]];
           for (int i = 0; i < 3; ++i)
             for (int j = 0; j < 3; ++j)
@@ -655,7 +661,7 @@ std::vector<double> colour_matrix_brute(int n) {
       }
       for (int si = 0; si < nf; ++si)
         for (int ti = 0; ti < nf; ++ti) {
-          std::complex<double> acc = 0;
+          std::complex<long double> acc = 0;
           for (int q = 0; q < 9; ++q) acc += std::conj(P[size_t(si) * 9 + q]) * P[size_t(ti) * 9 + q];
           Cl[size_t(si) * nf + ti] += acc;
         }
@@ -663,22 +669,22 @@ std::vector<double> colour_matrix_brute(int n) {
     std::lock_guard<std::mutex> lk(mtx);
     for (size_t q = 0; q < C.size(); ++q) C[q] += Cl[q];
   }
-  std::vector<double> out(C.size());
+  std::vector<long double> out(C.size());
   for (size_t q = 0; q < C.size(); ++q) out[q] = C[q].real();
   return out;
 }
 
 // sum over all colours of |sum_a (t^a)_{j i} (t^a)_{k l}|^2 (the colour
 // factor of q qbar -> t tbar), by brute force
-double qq_colour_factor() {
-  static const double v = [] {
-    const SU3& s = su3();
-    double acc = 0;
+long double qq_colour_factor() {
+  static const long double v = [] {
+    const SU3T<long double>& s = su3l();
+    long double acc = 0;
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j)
         for (int k = 0; k < 3; ++k)
           for (int l = 0; l < 3; ++l) {
-            std::complex<double> x = 0;
+            std::complex<long double> x = 0;
             for (int a = 0; a < 8; ++a) x += s.t[a][j][i] * s.t[a][k][l];
             acc += std::norm(x);
           }
@@ -691,12 +697,12 @@ double qq_colour_factor() {
 // colours, c_D = (t^a t^b)_{rc}(t^a)_{t tb}, (t^b t^a)_{rc}(t^a)_{t tb},
 // (t^a)_{rc}(t^b t^a)_{t tb}, (t^a)_{rc}(t^a t^b)_{t tb}, f^{abc'}(t^a)_{rc}(t^c')_{t tb}
 // (summed over a, c'), and M_{DE} = sum over r, c, t, tb, b of conj(c_D) c_E.
-const std::vector<std::complex<double>>& qqg_colour_matrix() {
-  static const std::vector<std::complex<double>> M = [] {
-    const SU3& s = su3();
-    std::vector<std::complex<double>> m(25, 0.0);
+const std::vector<std::complex<long double>>& qqg_colour_matrix() {
+  static const std::vector<std::complex<long double>> M = [] {
+    const SU3T<long double>& s = su3l();
+    std::vector<std::complex<long double>> m(25, 0.0L);
     auto prod = [&](int a, int b, int i, int j) {
-      std::complex<double> x = 0;
+      std::complex<long double> x = 0;
       for (int k = 0; k < 3; ++k) x += s.t[a][i][k] * s.t[b][k][j];
       return x;
     };
@@ -705,7 +711,7 @@ const std::vector<std::complex<double>>& qqg_colour_matrix() {
         for (int t = 0; t < 3; ++t)
           for (int tb = 0; tb < 3; ++tb)
             for (int b = 0; b < 8; ++b) {
-              std::complex<double> f[5] = {0, 0, 0, 0, 0};
+              std::complex<long double> f[5] = {0, 0, 0, 0, 0};
               for (int a = 0; a < 8; ++a) {
                 f[0] += prod(a, b, r, cl) * s.t[a][t][tb];
                 f[1] += prod(b, a, r, cl) * s.t[a][t][tb];
@@ -721,9 +727,9 @@ const std::vector<std::complex<double>>& qqg_colour_matrix() {
   return M;
 }
 
-const std::vector<double>& colour_matrix_cached(int n) {
+const std::vector<long double>& colour_matrix_cached(int n) {
   static std::mutex mtx;
-  static std::vector<double> cache[6];
+  static std::vector<long double> cache[6];
   std::lock_guard<std::mutex> lk(mtx);
   if (cache[n].empty()) cache[n] = colour_matrix_brute(n);
   return cache[n];
@@ -842,14 +848,30 @@ cx<T> dressed_amp(const Couplings<T>& c, const QcdEvent<T>& ev, const int* col) 
   return m;
 }
 
-template <class T> void load_event(const double* mom, int npar, T (*p)[4]) {
-  for (int i = 0; i < npar; ++i)
-    for (int m = 0; m < 4; ++m) p[i][m] = T(mom[i * 4 + m]);
+// Mass of leg i: the top quark and antiquark are legs 2 and 3 of every
+// process but e+ e- -> mu+ mu-; every other external particle is massless.
+double leg_mass(int proc, int i, double mt) { return proc != 0 && (i == 2 || i == 3) ? mt : 0.0; }
+
+// External momenta on the mass shell.  |M|^2 is defined for on-shell
+// momenta, and a double-precision input can only be on shell to rounding: its
+// energy component is therefore taken as sign(E) sqrt(m^2 + |p|^2), formed
+// in T from the given three-momentum.  (A massless leg nearly collinear with
+// a beam makes |M|^2 so sensitive to the off-shellness E - |p| of the input
+// that two exact evaluations which read E differently disagree far above
+// double rounding; with the projection the result is a function of the
+// three-momenta alone.)
+template <class T> void load_event(int proc, double mt, const double* mom, int npar, T (*p)[4]) {
+  for (int i = 0; i < npar; ++i) {
+    for (int m = 1; m < 4; ++m) p[i][m] = T(mom[i * 4 + m]);
+    const T mass = T(leg_mass(proc, i, mt));
+    const T e = std::sqrt(mass * mass + p[i][1] * p[i][1] + p[i][2] * p[i][2] + p[i][3] * p[i][3]);
+    p[i][0] = mom[i * 4] < 0 ? -e : e;
+  }
 }
 
 // Colour-summed |M_h|^2 for one helicity.
 template <class T>
-T me_hel(int proc, const Couplings<T>& c, const T (*p)[4], int hel, const std::vector<double>* C,
+T me_hel(int proc, const Couplings<T>& c, const T (*p)[4], int hel, const std::vector<long double>* C,
          std::vector<cx<T>>& A) {
   if (proc == 0) return std::norm(amp_eemumu(c, p, hel));
   if (is_qq(proc)) return T(qq_colour_factor()) * std::norm(amp_qqtt(c, p, hel, proc == 5 ? 0 : 1, proc == 5 ? 1 : 0));
@@ -874,7 +896,7 @@ void run_me(int proc, const oracle_params* prm, const double* mom, int64_t nevt,
   const int nhel = 1 << npar;
   const Couplings<T> c(*prm);
   const bool qcd_gluons = proc >= 1 && proc <= 4;
-  const std::vector<double>* C = qcd_gluons ? &colour_matrix_cached(ngluon_of(proc)) : nullptr;
+  const std::vector<long double>* C = qcd_gluons ? &colour_matrix_cached(ngluon_of(proc)) : nullptr;
   const int nf = qcd_gluons ? int(factorial(ngluon_of(proc))) : 1;
   const T iden = T(iden_of(proc));
 #ifdef _OPENMP
@@ -883,7 +905,7 @@ void run_me(int proc, const oracle_params* prm, const double* mom, int64_t nevt,
 #endif
   for (int64_t e = 0; e < nevt; ++e) {
     T p[7][4];
-    load_event(mom + size_t(e) * npar * 4, npar, p);
+    load_event(proc, prm->mt, mom + size_t(e) * npar * 4, npar, p);
     std::vector<cx<T>> A(nf);
     T tot = 0;
     for (int h = 0; h < nhel; ++h) {
@@ -1030,7 +1052,7 @@ int oracle_me_gauge(int proc, const oracle_params* p, const double* mom, int64_t
   const Couplings<double> c(*p);
   for (int64_t e = 0; e < nevt; ++e) {
     double pp[7][4];
-    load_event(mom + size_t(e) * 5 * 4, 5, pp);
+    load_event(proc, p->mt, mom + size_t(e) * 5 * 4, 5, pp);
     double tot = 0;
     for (int h = 0; h < 32; ++h) tot += qqg_me_hel(c, pp, proc, h, true);
     out[e] = tot / iden_of(proc);
@@ -1060,7 +1082,7 @@ int oracle_partial_amps(int proc, const oracle_params* prm, const double* mom, i
   if (npar < 0 || !prm || !mom || !out || hel < 0 || hel >= (1 << npar)) return -1;
   const Couplings<double> c(*prm);
   double p[7][4];
-  load_event(mom, npar, p);
+  load_event(proc, prm->mt, mom, npar, p);
   if (is_qqg(proc)) return -1;
   if (proc == 0 || is_qq(proc)) {
     if (gauge_leg >= 0) return -1;
@@ -1089,7 +1111,7 @@ int oracle_dressed_amp(int proc, const oracle_params* prm, const double* mom, in
   if (colours[ng] < 0 || colours[ng] > 2 || colours[ng + 1] < 0 || colours[ng + 1] > 2) return -1;
   const Couplings<double> c(*prm);
   double p[7][4];
-  load_event(mom, npar, p);
+  load_event(proc, prm->mt, mom, npar, p);
   QcdEvent<double> ev = qcd_setup(c, p, ng, hel, -1);
   std::complex<double> a = dressed_amp(c, ev, colours);
   out[0] = a.real(); out[1] = a.imag();
@@ -1106,8 +1128,8 @@ int oracle_colour_basis(int ngluons, const int* colours, double* out) {
 
 int oracle_colour_matrix(int ngluons, double* out) {
   if (ngluons < 1 || ngluons > 5 || !out) return -1;
-  const std::vector<double>& C = colour_matrix_cached(ngluons);
-  std::memcpy(out, C.data(), C.size() * sizeof(double));
+  const std::vector<long double>& C = colour_matrix_cached(ngluons);
+  for (size_t q = 0; q < C.size(); ++q) out[q] = double(C[q]);
   return 0;
 }
 
