@@ -121,6 +121,41 @@ __device__ __forceinline__ double msq(const double* K) {
 __device__ __forceinline__ double msq_lc(double kp, double km, double kx, double ky) {
   return kp * km - kx * kx - ky * ky;
 }
+// Light-cone components E + pz and E - pz of an on-shell momentum of mass m
+// (m^2 passed), each without cancellation: the small one of the two is
+// (m^2 + pT^2) divided by the large one.
+__device__ __forceinline__ double lc_plus(const double* p, double m2) {
+  return p[3] >= 0 ? p[0] + p[3] : (m2 + p[1] * p[1] + p[2] * p[2]) / (p[0] - p[3]);
+}
+__device__ __forceinline__ double lc_minus(const double* p, double m2) {
+  return p[3] <= 0 ? p[0] - p[3] : (m2 + p[1] * p[1] + p[2] * p[2]) / (p[0] + p[3]);
+}
+// (a + b)^2 = 2 a.b for two massless on-shell momenta, as
+// |E_b a_vec - E_a b_vec|^2 / (E_a E_b): the difference vector is small when
+// the two are nearly collinear and is formed with one rounding per component,
+// where E_a E_b - a_vec.b_vec would cancel.
+__device__ __forceinline__ double msq_pair0(const double* a, const double* b) {
+  const double wx = fma(b[0], a[1], -(a[0] * b[1]));
+  const double wy = fma(b[0], a[2], -(a[0] * b[2]));
+  const double wz = fma(b[0], a[3], -(a[0] * b[3]));
+  return (wx * wx + wy * wy + wz * wz) / (a[0] * b[0]);
+}
+// External momenta on the mass shell.  The energy component of each leg is
+// recomputed as sqrt(m^2 + |p|^2) (with the sign of the given one): a double
+// input is on shell only to rounding, and near collinear configurations the
+// result is sensitive to that rounding.  MASSIVE: bit i set if leg i has
+// mass mt.
+template <unsigned MASSIVE, int N>
+__device__ __forceinline__ void load_on_shell(const double* mom, double (&p)[N][4], double mt) {
+  const double2* src = reinterpret_cast<const double2*>(mom);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const double2 a = src[2 * i], b = src[2 * i + 1];
+    const double m2 = (MASSIVE >> i & 1u) ? mt * mt : 0.0;
+    p[i][1] = a.y; p[i][2] = b.x; p[i][3] = b.y;
+    p[i][0] = copysign(sqrt(m2 + a.y * a.y + b.x * b.x + b.y * b.y), a.x);
+  }
+}
 
 // Minkowski product of complex 4-vectors (no conjugation).
 // Either operand may be a wf or an epsw.

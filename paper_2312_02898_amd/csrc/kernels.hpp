@@ -35,12 +35,7 @@ __global__ __launch_bounds__(256) void me_kernel(const double* __restrict__ mom,
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= nevt) return;
   double p[P::NPAR][4];
-  const double2* src = reinterpret_cast<const double2*>(mom + e * (4 * P::NPAR));
-#pragma unroll
-  for (int i = 0; i < P::NPAR; ++i) {
-    const double2 a = src[2 * i], b = src[2 * i + 1];
-    p[i][0] = a.x; p[i][1] = a.y; p[i][2] = b.x; p[i][3] = b.y;
-  }
+  load_on_shell<P::MASSIVE>(mom + e * (4 * P::NPAR), p, prm.mt);
   double acc = 0.0;
   for (int ih = 0; ih < prm.nhel; ++ih) {
     // Momentum sums and propagator factors are recomputed per helicity where
@@ -122,12 +117,7 @@ __global__ __launch_bounds__(256) void me_kernel_kc(const double* __restrict__ m
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= nevt) return;
   double p[P::NPAR][4];
-  const double2* src = reinterpret_cast<const double2*>(mom + e * (4 * P::NPAR));
-#pragma unroll
-  for (int i = 0; i < P::NPAR; ++i) {
-    const double2 a = src[2 * i], b = src[2 * i + 1];
-    p[i][0] = a.x; p[i][1] = a.y; p[i][2] = b.x; p[i][3] = b.y;
-  }
+  load_on_shell<P::MASSIVE>(mom + e * (4 * P::NPAR), p, prm.mt);
   LdsKinCache<T> dc{kre, kcx, keps, int(threadIdx.x)};
   if constexpr (F64) P::template den_fill_f64<T>(p, prm, dc);
   else P::template den_fill_f32<T>(p, prm, dc);
@@ -170,12 +160,7 @@ __global__ __launch_bounds__(128) void me_kernel_ldsjamp(const double* __restric
   if (e >= nevt) return;
   LdsJamps<T> jamp{lds + wave * P::NCOLOR * 64 + lane};
   double p[P::NPAR][4];
-  const double2* src = reinterpret_cast<const double2*>(mom + e * (4 * P::NPAR));
-#pragma unroll
-  for (int i = 0; i < P::NPAR; ++i) {
-    const double2 a = src[2 * i], b = src[2 * i + 1];
-    p[i][0] = a.x; p[i][1] = a.y; p[i][2] = b.x; p[i][3] = b.y;
-  }
+  load_on_shell<P::MASSIVE>(mom + e * (4 * P::NPAR), p, prm.mt);
   double acc = 0.0;
   for (int ih = 0; ih < prm.nhel; ++ih) {
 #pragma unroll
@@ -208,12 +193,7 @@ __global__ __launch_bounds__(256) void me_kernel_mfma(const double* __restrict__
   const ColourA<P::NCOLOR> A = colour_a<P::NCOLOR>(P::cmat(), lane);
   const ColourA32<P::NCOLOR> A32 = colour_a32<P::NCOLOR>(P::cmat(), lane);
   double p[P::NPAR][4];
-  const double2* src = reinterpret_cast<const double2*>(mom + ec * (4 * P::NPAR));
-#pragma unroll
-  for (int i = 0; i < P::NPAR; ++i) {
-    const double2 a = src[2 * i], b = src[2 * i + 1];
-    p[i][0] = a.x; p[i][1] = a.y; p[i][2] = b.x; p[i][3] = b.y;
-  }
+  load_on_shell<P::MASSIVE>(mom + ec * (4 * P::NPAR), p, prm.mt);
   double acc = 0.0;
   for (int ih = 0; ih < prm.nhel; ++ih) {
 #pragma unroll

@@ -71,12 +71,7 @@ __global__ __launch_bounds__(256) void me_part_kernel(const double* __restrict__
   const int hc = blockIdx.y;
   const unsigned hel = prm.hel[h0 + hc];
   double p[P::NPAR][4];
-  const double2* src = reinterpret_cast<const double2*>(mom + e * (4 * P::NPAR));
-#pragma unroll
-  for (int i = 0; i < P::NPAR; ++i) {
-    const double2 a = src[2 * i], b = src[2 * i + 1];
-    p[i][0] = a.x; p[i][1] = a.y; p[i][2] = b.x; p[i][3] = b.y;
-  }
+  load_on_shell<P::MASSIVE>(mom + e * (4 * P::NPAR), p, prm.mt);
   P::template part<T, J>(p, hel, prm, X + int64_t(hc) * P::NCOLOR * ne_pad + e, ne_pad, qbuf + threadIdx.x * NQP);
 }
 

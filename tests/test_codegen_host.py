@@ -37,7 +37,7 @@ SHIM = r"""
 #define __builtin_amdgcn_sched_barrier(x) ((void)0)
 struct double2 { double x, y; };
 typedef int hipStream_t;
-using std::sqrt; using std::fabs;
+using std::sqrt; using std::fabs; using std::fma; using std::copysign;
 """
 
 MAIN = r"""
@@ -120,8 +120,13 @@ int main(int argc, char** argv) {
   prm.mt = 173.0; prm.wt = 1.49; prm.wt_tchan = 0.0;
   for (long e = 0; e < n; ++e) {
     double p[P::NPAR][4];
-    for (int i = 0; i < P::NPAR; ++i)
-      for (int c = 0; c < 4; ++c) p[i][c] = mom[(e * P::NPAR + i) * 4 + c];
+    // on the mass shell, as the kernels load them
+    for (int i = 0; i < P::NPAR; ++i) {
+      for (int c = 1; c < 4; ++c) p[i][c] = mom[(e * P::NPAR + i) * 4 + c];
+      const double m2 = (P::MASSIVE >> i & 1u) ? prm.mt * prm.mt : 0.0;
+      p[i][0] = std::copysign(std::sqrt(m2 + p[i][1] * p[i][1] + p[i][2] * p[i][2] + p[i][3] * p[i][3]),
+                              mom[(e * P::NPAR + i) * 4]);
+    }
     double acc = 0.0;
     for (unsigned h = 0; h < P::NHEL; ++h) {
       cx<T> J[P::NCOLOR];
