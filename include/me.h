@@ -11,8 +11,17 @@
  * colour sum jamp^H C jamp and the helicity sum.
  *
  * Supported processes (Summary section of the paper: LO QED/QCD; the
- * processes validated there are e+e- -> mu+mu- and gg -> ttbar + 0..3 g):
- *     "e+ e- > mu+ mu-"  "g g > t t~"  "g g > t t~ g"  "g g > t t~ g g"
+ * processes validated there are e+e- -> mu+mu- and gg -> ttbar + 0..3 g,
+ * and p p -> t tbar + jets is named as the next target):
+ *     "e+ e- > mu+ mu-"
+ *     "g g > t t~"  "g g > t t~ g"  "g g > t t~ g g"  "g g > t t~ g g g"
+ *     "u u~ > t t~"  "u~ u > t t~"                      (p p > t t~, quark channels)
+ *     "u u~ > t t~ g"  "u~ u > t t~ g"  "u g > t t~ u"  "g u > t t~ u"
+ *     "u~ g > t t~ u~"  "g u~ > t t~ u~"               (p p > t t~ + 1 jet)
+ * The short names "eemumu", "ggtt", "ggttg", "ggttgg", "ggttggg", "uutt",
+ * "uxutt", "uuttg", "uxuttg", "ugttu", "guttu", "uxgttux", "guxttux" are
+ * accepted too.  "g g > t t~ g g g" runs in a split form whose jamp
+ * workspace (me_workspace_bytes) comes from the stream-ordered allocator.
  *
  * Conventions
  *   momenta   const double mom[nevt][npar][4], (E, px, py, pz) in GeV, in
@@ -117,19 +126,35 @@ typedef struct {
 void me_default_params(me_sm_params* p);
 
 /* Create a handle for `process` (one of the strings above) with inputs *p on
- * the current HIP device.  Copies the constants the kernels need; *out
- * receives the handle.  ME_EPROCESS for an unknown process string. */
+ * the current HIP device.  The quantity it will compute is the LO |M|^2 of
+ * the process (paper, Sec. 2: the "matrix elements" that dominate madevent;
+ * Summary: LO QED and QCD), at the couplings, masses and widths of *p.
+ * Copies the constants the kernels need (they travel in each launch's
+ * argument block; the colour matrix is compiled in); *out receives the
+ * handle, which the caller releases with me_destroy.  ME_EPROCESS for an
+ * unknown process string, ME_EINVAL for null arguments or inputs out of
+ * range (non-positive couplings or masses of the Z, negative widths). */
 me_status me_create(const char* process, const me_sm_params* p, me_handle* out);
 
-/* Helicity filtering at initialisation: evaluates |M_h|^2 for all 2^npar
+/* Helicity filtering at initialisation.  The paper does not discuss
+ * helicities; skipping configurations whose |M_h|^2 vanishes leaves the
+ * |M|^2 of me_compute (paper, Sec. 2) unchanged and only removes work.
+ * Evaluates |M_h|^2 for all 2^npar
  * helicity configurations on filter_nevt RAMBO events at filter_sqrt_s
  * (centre-of-mass frame, seed filter_seed) in FP64 and keeps configuration h
  * iff max_events |M_h|^2 / sum_h' |M_h'|^2 > 1e-24.  Synchronous, idempotent.
  * Without it me_compute sums all 2^npar configurations (correct, slower). */
 me_status me_helicity_filter(me_handle h);
 
-/* |M|^2 for nevt events: d_momenta [nevt][npar][4] and d_me [nevt] are device
- * pointers, hip_stream a hipStream_t (NULL: default stream).  Asynchronous. */
+/* |M|^2 for nevt events (paper, Sec. 2: the same function evaluated for
+ * every event of a batch, in parallel over events): d_momenta [nevt][npar][4]
+ * and d_me [nevt] are device pointers owned by the caller, hip_stream a
+ * hipStream_t (NULL: default stream).  Asynchronous and stream-ordered;
+ * d_me holds 1/IDEN sum_helicities sum_colours |M|^2 (FP64, in every
+ * precision) once the stream is synchronised.  ME_EINVAL for a null handle or
+ * pointer or nevt < 0 (nothing is launched), ME_EHIP if a launch fails;
+ * nevt == 0 is a no-op.  Only "g g > t t~ g g g" allocates (its jamp
+ * workspace, stream-ordered: ME_ENOMEM if that fails). */
 me_status me_compute(me_handle h, const double* d_momenta, int64_t nevt, double* d_me,
                      void* hip_stream);
 
