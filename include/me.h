@@ -183,6 +183,12 @@ me_status me_compute_channels(const me_handle* handles, int32_t nchannels, const
                               const int32_t* d_channel, const double* d_alphas, int64_t nevt,
                               double* d_me, void* hip_stream);
 
+/* Device workspace bytes that me_compute allocates (stream-ordered) for nevt
+ * events of this handle: 0 for every process but "g g > t t~ g g g", whose
+ * split form keeps its jamps in a workspace of up to 1 GiB per call.
+ * ME_EINVAL for a null handle or pointer or nevt < 0. */
+me_status me_workspace_bytes(me_handle h, int64_t nevt, int64_t* bytes);
+
 /* Debugging: with the environment variable ME_DEBUG set (not "0") when a
  * handle is created, me_compute first checks every event on the device
  * (finite components, E >= 0, incoming = outgoing four-momentum within 1e-9

@@ -79,6 +79,7 @@ EXPORTS = [
     "me_good_helicities", "me_info", "me_destroy", "me_last_error",
     "me_server_create", "me_server_submit", "me_server_poll", "me_server_wait", "me_server_stats",
     "me_server_destroy", "me_max_weight", "me_rambo", "me_compute_channels", "me_server_times",
+    "me_workspace_bytes",
 ]
 
 _lib = None
@@ -108,6 +109,7 @@ def lib():
         L.me_max_weight.argtypes = [vp, vp, i64, vp, vp, vp]
         L.me_rambo.argtypes = [i64, i32, P(d), d, ctypes.c_uint64, vp, vp]
         L.me_compute_channels.argtypes = [P(vp), i32, vp, vp, vp, i64, vp, vp]
+        L.me_workspace_bytes.argtypes = [vp, i64, P(i64)]
         if hasattr(L, "me_server_create"):
             L.me_server_create.argtypes = [i64, i32, P(vp)]
             L.me_server_submit.argtypes = [vp, vp, vp, i64, vp, P(i64)]
@@ -194,6 +196,13 @@ def me_compute_channels(handles, d_momenta: int, d_channel: int, d_alphas: int, 
                                      int(nevt), d_out or None, stream or None), "me_compute_channels")
 
 
+def me_workspace_bytes(handle: int, nevt: int) -> int:
+    """Device workspace me_compute allocates for nevt events of this handle."""
+    b = ctypes.c_int64()
+    _check(lib().me_workspace_bytes(handle, int(nevt), ctypes.byref(b)), "me_workspace_bytes")
+    return b.value
+
+
 def me_last_error() -> str:
     return lib().me_last_error().decode(errors="replace")
 
@@ -212,6 +221,11 @@ def me_server_submit(server: int, handle: int, h_momenta: np.ndarray, h_out: np.
         raise ValueError("h_momenta must be C-contiguous float64")
     if h_out.dtype != np.float64 or not h_out.flags.c_contiguous:
         raise ValueError("h_out must be C-contiguous float64")
+    npar = me_info(handle)["npar"]
+    if h_momenta.ndim != 3 or h_momenta.shape[1] != npar or h_momenta.shape[2] != 4:
+        raise ValueError(f"h_momenta must have shape [nevt][{npar}][4]")
+    if h_out.ndim != 1 or h_out.shape[0] < h_momenta.shape[0]:
+        raise ValueError("h_out must hold nevt elements")
     t = ctypes.c_int64()
     _check(lib().me_server_submit(server, handle, h_momenta.ctypes.data, h_momenta.shape[0], h_out.ctypes.data,
                                   ctypes.byref(t)), "me_server_submit")

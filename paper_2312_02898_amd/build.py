@@ -76,6 +76,7 @@ def build(processes=None, jobs=None, verbose=True) -> str:
     units.append((os.path.join(CSRC, "runtime.cpp"), hdrs + [table, os.path.join(ROOT, "include", "me.h"),
                                                              os.path.join(CSRC, "channels.hpp"),
                                                              os.path.join(CSRC, "handle.hpp")]))
+    hdrs = hdrs + [os.path.join(CSRC, "handle.hpp")]
     for extra in ("server.cpp", "unweight.cpp", "rambo.cpp", "channels.cpp"):
         units.append((os.path.join(CSRC, extra),
                       hdrs + [os.path.join(CSRC, "server_core.hpp"), os.path.join(CSRC, "channels.hpp"),

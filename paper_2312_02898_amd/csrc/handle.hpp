@@ -1,5 +1,7 @@
 // The handle behind the C ABI (internal to the library).
 #pragma once
+#include <string>
+
 #include "me.h"
 #include "me_types.h"
 
@@ -28,5 +30,16 @@ inline int mode_of(const me_sm_params& p) {
 // within 1e-9 of the incoming energy.  Returns the number of bad events
 // (synchronises the stream); negative on a HIP error.
 int64_t validate_momenta(const double* d_mom, int64_t nevt, int npar, hipStream_t s);
+
+// Records code and message for me_last_error(); returns code.
+me_status set_error(me_status code, const std::string& msg);
+
+// me_compute_channels with an optional caller workspace: ws == NULL takes the
+// workspace from the stream-ordered allocator; otherwise ws_bytes must cover
+// chan::workspace_bytes() and every channel's launch must need no workspace
+// of its own (nothing is allocated).  `who` prefixes error messages.
+me_status compute_channels_on(const me_handle* handles, int32_t nchannels, const double* d_momenta,
+                              const int32_t* d_channel, const double* d_alphas, int64_t nevt, double* d_me,
+                              hipStream_t s, void* ws, int64_t ws_bytes, const char* who);
 
 }  // namespace me

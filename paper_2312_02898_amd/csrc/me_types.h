@@ -21,8 +21,16 @@ struct MeParams {
   uint8_t hel[128]; // helicity configurations: bit i = leg i has helicity +1
 };
 
+// Launch of one process's kernels.  ws / ws_bytes: device workspace for the
+// forms that need one (the split form); NULL lets the launch take it from the
+// stream-ordered allocator.  0 on success, -1 bad arguments, -2 launch
+// failure, -3 workspace allocation failed or too small.
 typedef int (*LaunchFn)(int mode, const double* mom, int64_t nevt, double* out, double* out_hel,
-                        const MeParams* prm, hipStream_t stream);
+                        const MeParams* prm, hipStream_t stream, void* ws, int64_t ws_bytes);
+// Device workspace bytes a launch of nevt events with nhel helicities needs
+// when it may use at most cap bytes (cap <= 0: the launch's own default);
+// 0 for the forms that need none.
+typedef int64_t (*WorkspaceFn)(int mode, int64_t nevt, int nhel, int64_t cap);
 
 struct ProcessEntry {
   const char* name;
@@ -32,6 +40,7 @@ struct ProcessEntry {
   int massive_top;     // legs 2 and 3 carry the top mass
   int alphas_power;    // |M|^2 is proportional to alpha_s^alphas_power
   LaunchFn launch;
+  WorkspaceFn workspace;
 };
 
 }  // namespace me

@@ -107,6 +107,75 @@ void rambo_event(SplitMix64& rng, double sqrt_s, const std::vector<double>& mass
 
 }  // namespace
 
+namespace me {
+
+me_status set_error(me_status code, const std::string& msg) { return fail(code, msg); }
+
+me_status compute_channels_on(const me_handle* handles, int32_t nchannels, const double* d_momenta,
+                              const int32_t* d_channel, const double* d_alphas, int64_t nevt, double* d_me,
+                              hipStream_t s, void* ws, int64_t ws_bytes, const char* who) {
+  const std::string w_ = who;
+  if (!handles || nchannels < 1 || nchannels > chan::kMaxChannels) return fail(ME_EINVAL, w_ + ": need 1..32 handles");
+  for (int c = 0; c < nchannels; ++c)
+    if (!handles[c]) return fail(ME_EINVAL, w_ + ": null handle");
+  const int npar = handles[0]->proc->npar;
+  for (int c = 1; c < nchannels; ++c)
+    if (handles[c]->proc->npar != npar)
+      return fail(ME_EINVAL, w_ + ": channels must have the same number of legs");
+  if (nevt < 0) return fail(ME_EINVAL, w_ + ": nevt < 0");
+  if (nevt == 0) return ME_OK;
+  if (!d_momenta || !d_channel || !d_me) return fail(ME_EINVAL, w_ + ": null pointer");
+  const size_t need = chan::workspace_bytes(nevt, nchannels, npar);
+  void* base = ws;
+  if (ws) {
+    // a caller workspace: nothing may allocate
+    if (ws_bytes < 0 || size_t(ws_bytes) < need)
+      return fail(ME_EINVAL, w_ + ": " + std::to_string(nevt) + " events need " + std::to_string(need) +
+                                 " bytes of workspace, more than the " + std::to_string(ws_bytes) + " available");
+    for (int c = 0; c < nchannels; ++c)
+      if (handles[c]->proc->workspace(mode_of(handles[c]->params), 1, handles[c]->kp.nhel, 0) > 0)
+        return fail(ME_ENOTSUP, w_ + ": process '" + handles[c]->proc->process +
+                                    "' needs a workspace of its own (split form)");
+  } else if (hipMallocAsync(&base, need, s) != hipSuccess) {
+    return fail(ME_ENOMEM, w_ + ": no device memory for the workspace");
+  }
+  const chan::Workspace w = chan::carve(base, nevt, nchannels, npar);
+  int64_t totals[chan::kMaxChannels];
+  int32_t bad = 0;
+  hipError_t err = chan::partition(d_channel, nevt, nchannels, w, totals, &bad, s);
+  if (err != hipSuccess || bad) {
+    if (!ws) (void)hipFreeAsync(base, s);
+    if (err != hipSuccess) return hip_fail(err, (w_ + ": partition").c_str());
+    return fail(ME_EINVAL, w_ + ": channel index out of range");
+  }
+  chan::Scale sc;
+  int64_t off = 0;
+  int rc = 0;
+  for (int c = 0; c < nchannels; ++c) {
+    sc.aref[c] = handles[c]->params.alpha_s;
+    sc.power[c] = handles[c]->proc->alphas_power;
+    if (totals[c] == 0) continue;
+    err = chan::gather(d_momenta, w.perm + off, totals[c], npar, w.mom + off * 4 * npar, s);
+    if (err != hipSuccess) break;
+    const me_handle h = handles[c];
+    rc = h->proc->launch(mode_of(h->params), w.mom + off * 4 * npar, totals[c], w.out + off, nullptr, &h->kp, s,
+                         nullptr, 0);
+    if (rc != 0) {
+      err = hipGetLastError();
+      if (err == hipSuccess) err = hipErrorLaunchFailure;
+      break;
+    }
+    off += totals[c];
+  }
+  if (err == hipSuccess) err = chan::scatter(w.out, w.perm, d_channel, d_alphas, sc, nevt, d_me, s);
+  if (!ws) (void)hipFreeAsync(base, s);
+  if (rc == -3) return fail(ME_ENOMEM, w_ + ": no device memory for a channel's workspace");
+  if (err != hipSuccess) return hip_fail(err, w_.c_str());
+  return ME_OK;
+}
+
+}  // namespace me
+
 
 extern "C" {
 
@@ -193,7 +262,7 @@ me_status me_helicity_filter(me_handle h) {
   for (int i = 0; i < nhel; ++i) all.hel[i] = uint8_t(i);
   int rc = -1;
   he = hipMemcpy(d_mom, mom.data(), mom.size() * sizeof(double), hipMemcpyHostToDevice);
-  if (he == hipSuccess) rc = e->launch(me::ME_MODE_FP64, d_mom, n, nullptr, d_hel, &all, nullptr);
+  if (he == hipSuccess) rc = e->launch(me::ME_MODE_FP64, d_mom, n, nullptr, d_hel, &all, nullptr, nullptr, 0);
   if (he == hipSuccess && rc == 0) he = hipMemcpy(mh.data(), d_hel, mh.size() * sizeof(double), hipMemcpyDeviceToHost);
   (void)hipFree(d_mom);
   (void)hipFree(d_hel);
@@ -229,7 +298,8 @@ me_status me_compute(me_handle h, const double* d_momenta, int64_t nevt, double*
                                  " events with non-finite components, negative energy or unbalanced momentum");
   }
   int rc = h->proc->launch(me::mode_of(h->params), d_momenta, nevt, d_me, nullptr, &h->kp,
-                           static_cast<hipStream_t>(hip_stream));
+                           static_cast<hipStream_t>(hip_stream), nullptr, 0);
+  if (rc == -3) return fail(ME_ENOMEM, "me_compute: no device memory for the workspace");
   if (rc != 0) {
     hipError_t le = hipGetLastError();
     return fail(ME_EHIP, std::string("me_compute: launch failed: ") + hipGetErrorString(le));
@@ -237,54 +307,17 @@ me_status me_compute(me_handle h, const double* d_momenta, int64_t nevt, double*
   return ME_OK;
 }
 
+me_status me_workspace_bytes(me_handle h, int64_t nevt, int64_t* bytes) {
+  if (!h || !bytes || nevt < 0) return fail(ME_EINVAL, "me_workspace_bytes: bad argument");
+  *bytes = h->proc->workspace(me::mode_of(h->params), nevt, h->kp.nhel, 0);
+  return ME_OK;
+}
+
 me_status me_compute_channels(const me_handle* handles, int32_t nchannels, const double* d_momenta,
                               const int32_t* d_channel, const double* d_alphas, int64_t nevt, double* d_me,
                               void* hip_stream) {
-  if (!handles || nchannels < 1 || nchannels > me::chan::kMaxChannels)
-    return fail(ME_EINVAL, "me_compute_channels: need 1..32 handles");
-  for (int c = 0; c < nchannels; ++c)
-    if (!handles[c]) return fail(ME_EINVAL, "me_compute_channels: null handle");
-  const int npar = handles[0]->proc->npar;
-  for (int c = 1; c < nchannels; ++c)
-    if (handles[c]->proc->npar != npar)
-      return fail(ME_EINVAL, "me_compute_channels: channels must have the same number of legs");
-  if (nevt < 0) return fail(ME_EINVAL, "me_compute_channels: nevt < 0");
-  if (nevt == 0) return ME_OK;
-  if (!d_momenta || !d_channel || !d_me) return fail(ME_EINVAL, "me_compute_channels: null pointer");
-  hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  void* base = nullptr;
-  if (hipMallocAsync(&base, me::chan::workspace_bytes(nevt, nchannels, npar), s) != hipSuccess)
-    return fail(ME_ENOMEM, "me_compute_channels: no device memory for the workspace");
-  const me::chan::Workspace w = me::chan::carve(base, nevt, nchannels, npar);
-  int64_t totals[me::chan::kMaxChannels];
-  int32_t bad = 0;
-  hipError_t err = me::chan::partition(d_channel, nevt, nchannels, w, totals, &bad, s);
-  if (err != hipSuccess || bad) {
-    (void)hipFreeAsync(base, s);
-    if (err != hipSuccess) return hip_fail(err, "me_compute_channels: partition");
-    return fail(ME_EINVAL, "me_compute_channels: channel index out of range");
-  }
-  me::chan::Scale sc;
-  int64_t off = 0;
-  for (int c = 0; c < nchannels; ++c) {
-    sc.aref[c] = handles[c]->params.alpha_s;
-    sc.power[c] = handles[c]->proc->alphas_power;
-    if (totals[c] == 0) continue;
-    err = me::chan::gather(d_momenta, w.perm + off, totals[c], npar, w.mom + off * 4 * npar, s);
-    if (err != hipSuccess) break;
-    const me_handle h = handles[c];
-    if (h->proc->launch(me::mode_of(h->params), w.mom + off * 4 * npar, totals[c], w.out + off, nullptr, &h->kp,
-                        s) != 0) {
-      err = hipGetLastError();
-      if (err == hipSuccess) err = hipErrorLaunchFailure;
-      break;
-    }
-    off += totals[c];
-  }
-  if (err == hipSuccess) err = me::chan::scatter(w.out, w.perm, d_channel, d_alphas, sc, nevt, d_me, s);
-  (void)hipFreeAsync(base, s);
-  if (err != hipSuccess) return hip_fail(err, "me_compute_channels");
-  return ME_OK;
+  return me::compute_channels_on(handles, nchannels, d_momenta, d_channel, d_alphas, nevt, d_me,
+                                 static_cast<hipStream_t>(hip_stream), nullptr, 0, "me_compute_channels");
 }
 
 me_status me_compute_helicities(me_handle h, const double* d_momenta, int64_t nevt, double* d_me_hel,
@@ -297,7 +330,7 @@ me_status me_compute_helicities(me_handle h, const double* d_momenta, int64_t ne
   all.nhel = h->proc->nhel;
   for (int i = 0; i < all.nhel; ++i) all.hel[i] = uint8_t(i);
   int rc = h->proc->launch(me::ME_MODE_FP64, d_momenta, nevt, nullptr, d_me_hel, &all,
-                           static_cast<hipStream_t>(hip_stream));
+                           static_cast<hipStream_t>(hip_stream), nullptr, 0);
   if (rc != 0) return fail(ME_EHIP, "me_compute_helicities: launch failed");
   return ME_OK;
 }

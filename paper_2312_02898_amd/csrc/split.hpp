@@ -250,23 +250,49 @@ __global__ __launch_bounds__(256) void me_colour_split_f64(const cx<double>* __r
   if (out && live && g == 0) out[e] = (accumulate ? out[e] : 0.0) + acc * (f / P::IDEN);
 }
 
-// Events per chunk and workspace cap per call; the workspace comes from the
-// stream-ordered allocator, so concurrent calls on different streams each
-// get their own.
+// Events per chunk and the default workspace cap per call.  Without a
+// caller workspace the launch takes it from the stream-ordered allocator, so
+// concurrent calls on different streams each get their own.
 constexpr int64_t kSplitChunkEvents = int64_t(1) << 17;
-constexpr size_t kSplitWorkspaceBytes = size_t(1) << 30;
+constexpr int64_t kSplitWorkspaceBytes = int64_t(1) << 30;
+
+// Bytes of one helicity slot of the jamp workspace for a chunk of nevt events.
+template <class P, class T> int64_t split_row_bytes(int64_t nevt) {
+  const int64_t ne_max = nevt < kSplitChunkEvents ? nevt : kSplitChunkEvents;
+  const int64_t ne_pad = (ne_max + 255) / 256 * 256;
+  return int64_t(P::NCOLOR) * int64_t(sizeof(cx<T>)) * ne_pad;
+}
+// Helicity slots a workspace of `bytes` holds (at most nhel, at least 1).
+template <class P, class T> int64_t split_slots(int64_t nevt, int nhel, int64_t bytes) {
+  int64_t nh = bytes / split_row_bytes<P, T>(nevt);
+  if (nh > nhel && nhel > 0) nh = nhel;
+  return nh < 1 ? 1 : nh;
+}
+// Workspace of a launch that may use at most cap bytes (cap <= 0: default).
+template <class P>
+int64_t split_workspace_bytes(int mode, int64_t nevt, int nhel, int64_t cap) {
+  if (nevt <= 0) return 0;
+  if (cap <= 0) cap = kSplitWorkspaceBytes;
+  if (mode == ME_MODE_FP64) return split_row_bytes<P, double>(nevt) * split_slots<P, double>(nevt, nhel, cap);
+  return split_row_bytes<P, float>(nevt) * split_slots<P, float>(nevt, nhel, cap);
+}
 
 template <class P, class T>
 int run_split(const double* mom, int64_t nevt, double* out, double* out_hel, const MeParams& prm,
-              hipStream_t stream, const PartLaunchFn* parts, int nparts) {
+              hipStream_t stream, void* ws, int64_t ws_bytes, const PartLaunchFn* parts, int nparts) {
   const int64_t ne_max = nevt < kSplitChunkEvents ? nevt : kSplitChunkEvents;
   const int64_t ne_pad = (ne_max + 255) / 256 * 256;
-  const size_t row = size_t(P::NCOLOR) * sizeof(cx<T>) * size_t(ne_pad);   // one helicity slot
-  int64_t nh = int64_t(kSplitWorkspaceBytes / row);
-  if (nh < 1) nh = 1;
-  if (nh > prm.nhel && prm.nhel > 0) nh = prm.nhel;
-  cx<T>* X = nullptr;
-  if (hipMallocAsync(reinterpret_cast<void**>(&X), row * size_t(nh), stream) != hipSuccess) return -3;
+  const int64_t row = split_row_bytes<P, T>(nevt);   // one helicity slot
+  cx<T>* X = static_cast<cx<T>*>(ws);
+  int64_t nh;
+  if (X) {
+    // the caller's workspace: as many helicity slots as it holds
+    if (ws_bytes < row) return -3;
+    nh = split_slots<P, T>(nevt, prm.nhel, ws_bytes);
+  } else {
+    nh = split_slots<P, T>(nevt, prm.nhel, kSplitWorkspaceBytes);
+    if (hipMallocAsync(reinterpret_cast<void**>(&X), size_t(row) * size_t(nh), stream) != hipSuccess) return -3;
+  }
   for (int64_t e0 = 0; e0 < nevt; e0 += kSplitChunkEvents) {
     const int64_t ne = nevt - e0 < kSplitChunkEvents ? nevt - e0 : kSplitChunkEvents;
     // with no helicity left the colour kernel still runs once and writes zeros
@@ -287,7 +313,7 @@ int run_split(const double* mom, int64_t nevt, double* out, double* out_hel, con
     }
   }
   const hipError_t err = hipGetLastError();
-  (void)hipFreeAsync(X, stream);
+  if (!ws) (void)hipFreeAsync(X, stream);
   return err == hipSuccess ? 0 : -2;
 }
 
@@ -295,15 +321,17 @@ int run_split(const double* mom, int64_t nevt, double* out, double* out_hel, con
 // or one of the mixed modes (FP32 parts, FP16 hi/lo MFMA colour sum).
 template <class P>
 int launch_split(int mode, const double* mom, int64_t nevt, double* out, double* out_hel, const MeParams& prm,
-                 hipStream_t stream, const PartLaunchFn* parts64, int n64, const PartLaunchFn* parts32, int n32) {
+                 hipStream_t stream, void* ws, int64_t ws_bytes, const PartLaunchFn* parts64, int n64,
+                 const PartLaunchFn* parts32, int n32) {
   if (nevt <= 0) return 0;
   if ((nevt + 255) / 256 > 0x7fffffffLL) return -1;
-  if (mode == ME_MODE_FP64) return run_split<P, double>(mom, nevt, out, out_hel, prm, stream, parts64, n64);
+  if (mode == ME_MODE_FP64)
+    return run_split<P, double>(mom, nevt, out, out_hel, prm, stream, ws, ws_bytes, parts64, n64);
   if (mode != ME_MODE_MIXED && mode != ME_MODE_MIXED_VALU && mode != ME_MODE_MIXED_MFMA32 &&
       mode != ME_MODE_MIXED_MFMA16)
     return -1;
   if (out_hel || !out) return -1;
-  return run_split<P, float>(mom, nevt, out, nullptr, prm, stream, parts32, n32);
+  return run_split<P, float>(mom, nevt, out, nullptr, prm, stream, ws, ws_bytes, parts32, n32);
 }
 
 }  // namespace me

@@ -31,17 +31,28 @@ class ChannelMix:
 
     def __init__(self, processes, precision: str = "fp64", filter_helicities: bool = True, **params):
         self.members = [MatrixElement(p, precision, filter_helicities, **params) for p in processes]
+        self.call = B.me_compute_channels
 
     def __call__(self, momenta: torch.Tensor, channel: torch.Tensor, alphas: torch.Tensor | None = None,
                  out: torch.Tensor | None = None) -> torch.Tensor:
+        npar = self.members[0].info["npar"]
+        if momenta.dtype != torch.float64 or not momenta.is_cuda or not momenta.is_contiguous():
+            raise ValueError("momenta must be a contiguous float64 CUDA tensor [nevt][npar][4]")
+        if momenta.dim() != 3 or momenta.shape[1] != npar or momenta.shape[2] != 4:
+            raise ValueError(f"momenta must have shape [nevt][{npar}][4]")
         n = momenta.shape[0]
+        if channel.shape != (n,) or not channel.is_cuda or channel.device != momenta.device:
+            raise ValueError("channel must be a CUDA tensor of nevt integers on the momenta's device")
+        if alphas is not None and (alphas.shape != (n,) or not alphas.is_cuda or alphas.device != momenta.device):
+            raise ValueError("alphas must be a CUDA tensor of nevt values on the momenta's device")
         if out is None:
             out = torch.empty(n, dtype=torch.float64, device=momenta.device)
+        elif out.dtype != torch.float64 or not out.is_cuda or not out.is_contiguous() or out.numel() < n:
+            raise ValueError("out must be a contiguous float64 CUDA tensor with nevt elements")
         ch = channel.to(dtype=torch.int32).contiguous()
         a = alphas.to(dtype=torch.float64).contiguous() if alphas is not None else None
-        B.me_compute_channels([m.handle for m in self.members], momenta.data_ptr(), ch.data_ptr(),
-                              a.data_ptr() if a is not None else 0, n, out.data_ptr(),
-                              torch.cuda.current_stream().cuda_stream)
+        self.call([m.handle for m in self.members], momenta.data_ptr(), ch.data_ptr(),
+                  a.data_ptr() if a is not None else 0, n, out.data_ptr(), torch.cuda.current_stream().cuda_stream)
         return out
 
     def close(self):
@@ -80,6 +91,10 @@ class MatrixElement:
         return out
 
     def helicities(self, momenta: torch.Tensor) -> torch.Tensor:
+        if momenta.dtype != torch.float64 or not momenta.is_cuda or not momenta.is_contiguous():
+            raise ValueError("momenta must be a contiguous float64 CUDA tensor [nevt][npar][4]")
+        if momenta.dim() != 3 or momenta.shape[1] != self.info["npar"] or momenta.shape[2] != 4:
+            raise ValueError(f"momenta must have shape [nevt][{self.info['npar']}][4]")
         n = momenta.shape[0]
         out = torch.empty((n, self.info["nhel"]), dtype=torch.float64, device=momenta.device)
         B.me_compute_helicities(self.handle, momenta.data_ptr(), n, out.data_ptr(),
