@@ -189,6 +189,25 @@ me_status me_compute_channels(const me_handle* handles, int32_t nchannels, const
  * ME_EINVAL for a null handle or pointer or nevt < 0. */
 me_status me_workspace_bytes(me_handle h, int64_t nevt, int64_t* bytes);
 
+/* Size of the fixed device workspace of me_compute_channels_noalloc. */
+#define ME_NOALLOC_SCRATCH_BYTES (64ll << 20)
+
+/* For callers that cannot allocate device memory (code under HIP stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * call and result as me_compute_channels, with its workspace (about
+ * 32 npar + 16 bytes per event) in a fixed device array of
+ * ME_NOALLOC_SCRATCH_BYTES per device instead of the stream-ordered
+ * allocator.  Nothing is allocated: a batch whose workspace would exceed the
+ * array gives ME_EINVAL (nothing is launched), a handle whose process needs
+ * a workspace of its own ("g g > t t~ g g g") ME_ENOTSUP.  The array is
+ * shared by every call on a device and keeps the last call's contents:
+ * calls that overlap on one device (other streams or threads) race and
+ * must be serialised by the caller.  Like me_compute_channels it waits once
+ * for the per-channel counts. */
+me_status me_compute_channels_noalloc(const me_handle* handles, int32_t nchannels, const double* d_momenta,
+                                      const int32_t* d_channel, const double* d_alphas, int64_t nevt,
+                                      double* d_me, void* hip_stream);
+
 /* Debugging: with the environment variable ME_DEBUG set (not "0") when a
  * handle is created, me_compute first checks every event on the device
  * (finite components, E >= 0, incoming = outgoing four-momentum within 1e-9

@@ -79,8 +79,11 @@ EXPORTS = [
     "me_good_helicities", "me_info", "me_destroy", "me_last_error",
     "me_server_create", "me_server_submit", "me_server_poll", "me_server_wait", "me_server_stats",
     "me_server_destroy", "me_max_weight", "me_rambo", "me_compute_channels", "me_server_times",
-    "me_workspace_bytes",
+    "me_workspace_bytes", "me_compute_channels_noalloc",
 ]
+
+# fixed device workspace of me_compute_channels_noalloc (ME_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 _lib = None
 
@@ -109,6 +112,7 @@ def lib():
         L.me_max_weight.argtypes = [vp, vp, i64, vp, vp, vp]
         L.me_rambo.argtypes = [i64, i32, P(d), d, ctypes.c_uint64, vp, vp]
         L.me_compute_channels.argtypes = [P(vp), i32, vp, vp, vp, i64, vp, vp]
+        L.me_compute_channels_noalloc.argtypes = [P(vp), i32, vp, vp, vp, i64, vp, vp]
         L.me_workspace_bytes.argtypes = [vp, i64, P(i64)]
         if hasattr(L, "me_server_create"):
             L.me_server_create.argtypes = [i64, i32, P(vp)]
@@ -194,6 +198,16 @@ def me_compute_channels(handles, d_momenta: int, d_channel: int, d_alphas: int, 
     arr = (ctypes.c_void_p * len(handles))(*handles)
     _check(lib().me_compute_channels(arr, len(handles), d_momenta or None, d_channel or None, d_alphas or None,
                                      int(nevt), d_out or None, stream or None), "me_compute_channels")
+
+
+def me_compute_channels_noalloc(handles, d_momenta: int, d_channel: int, d_alphas: int, nevt: int, d_out: int,
+                                stream: int = 0) -> None:
+    """me_compute_channels with its workspace in the library's fixed device
+    array (nothing is allocated; calls that overlap on one device race)."""
+    arr = (ctypes.c_void_p * len(handles))(*handles)
+    _check(lib().me_compute_channels_noalloc(arr, len(handles), d_momenta or None, d_channel or None,
+                                             d_alphas or None, int(nevt), d_out or None, stream or None),
+           "me_compute_channels_noalloc")
 
 
 def me_workspace_bytes(handle: int, nevt: int) -> int:

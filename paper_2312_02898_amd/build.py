@@ -77,7 +77,7 @@ def build(processes=None, jobs=None, verbose=True) -> str:
                                                              os.path.join(CSRC, "channels.hpp"),
                                                              os.path.join(CSRC, "handle.hpp")]))
     hdrs = hdrs + [os.path.join(CSRC, "handle.hpp")]
-    for extra in ("server.cpp", "unweight.cpp", "rambo.cpp", "channels.cpp"):
+    for extra in ("server.cpp", "unweight.cpp", "rambo.cpp", "channels.cpp", "noalloc.cpp"):
         units.append((os.path.join(CSRC, extra),
                       hdrs + [os.path.join(CSRC, "server_core.hpp"), os.path.join(CSRC, "channels.hpp"),
                               os.path.join(ROOT, "include", "me.h")]))

@@ -29,9 +29,12 @@ class ChannelMix:
     evaluated by channel[e] (an index into `processes`), optionally at its own
     alpha_s."""
 
-    def __init__(self, processes, precision: str = "fp64", filter_helicities: bool = True, **params):
+    def __init__(self, processes, precision: str = "fp64", filter_helicities: bool = True, noalloc: bool = False,
+                 **params):
         self.members = [MatrixElement(p, precision, filter_helicities, **params) for p in processes]
-        self.call = B.me_compute_channels
+        # noalloc: the entry point whose workspace is the library's fixed
+        # device array (for callers that cannot allocate)
+        self.call = B.me_compute_channels_noalloc if noalloc else B.me_compute_channels
 
     def __call__(self, momenta: torch.Tensor, channel: torch.Tensor, alphas: torch.Tensor | None = None,
                  out: torch.Tensor | None = None) -> torch.Tensor:
