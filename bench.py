@@ -415,7 +415,9 @@ def main():
             cap[nm] = 65536 / (a.elapsed_time(b) * 1e-3)
         # processes drawn uniformly, sizes log-uniform in [256, 65536]:
         # offered loads 0.5, 0.7, 0.9 of the capacity measured above, and a
-        # small arena (64 MiB) at 0.7 so that admission by memory engages
+        # small arena (256 MiB) at 0.7 so that admission by memory engages;
+        # every request's footprint holds its momenta, results and (g g > t t~
+        # g g g) jamp workspace
         mean_events = (65536 - 256) / np.log(65536 / 256)
         sec_per_request = mean_events * np.mean([1.0 / cap[nm] for nm in names])
 
@@ -443,9 +445,10 @@ def main():
                     "queue_ms": {"p50": float(np.median(q) * 1e3), "p99": float(np.quantile(q, 0.99) * 1e3)},
                     "service_ms": {"p50": float(np.median(sv) * 1e3), "p99": float(np.quantile(sv, 0.99) * 1e3)},
                     "throughput_ME_s": ev / wall, "failed": int((status != 0).sum()),
-                    "peak_bytes_in_use": st["peak_bytes_in_use"], "per_process": per}
+                    "peak_bytes_in_use": st["peak_bytes_in_use"], "admissions_past_waiting_head": st["bypassed"],
+                    "per_process": per}
 
-        runs = [serve(0.7, 4 << 30), serve(0.5, 4 << 30), serve(0.9, 4 << 30), serve(0.7, 64 << 20)]
+        runs = [serve(0.7, 4 << 30), serve(0.5, 4 << 30), serve(0.9, 4 << 30), serve(0.7, 256 << 20)]
         head = runs[0]
         rec["serving"] = {"requests": head["requests"], "p50_latency_ms": head["p50_latency_ms"],
                           "p99_latency_ms": head["p99_latency_ms"], "throughput_ME_s": head["throughput_ME_s"],

@@ -256,12 +256,18 @@ me_status me_rambo(int64_t nevt, int32_t nfinal, const double* masses, double sq
 
 /* ------------------------------------------------------------ serving --
  * A persistent request loop for uneven |M|^2 batches of several processes,
- * as integration channels emit them (continuous batching).  Requests are
- * admitted in arrival order as stream slots and device memory (budget_bytes,
- * counting each request's device momenta + output) free up; admitted work on
- * different slots overlaps on the device.  Host buffers: the server stages
- * momenta to device memory and results back.  Handles must be filtered
- * before submission and stay alive while their requests are in flight.
+ * as integration channels emit them (continuous batching).  A request's
+ * device footprint is its momenta, its results and the workspace its
+ * process needs ("g g > t t~ g g g": the jamp workspace, capped per request
+ * at a quarter of budget_bytes and at most 256 MiB), all carved from one
+ * device arena of budget_bytes allocated at creation; nothing is allocated
+ * per request.  Requests are admitted in arrival order as stream slots and
+ * arena memory free up; when the head of the queue waits for memory, at
+ * most 16 later requests that fit may pass it before the queue is strictly
+ * in order again.  Admitted work on different slots overlaps on the device.
+ * Host buffers: the server stages momenta to device memory and results
+ * back.  Handles must be filtered before submission and stay alive while
+ * their requests are in flight.
  */
 typedef struct me_server_s* me_server;
 
@@ -270,6 +276,7 @@ typedef struct {
   int64_t events_completed;
   int64_t bytes_in_use, peak_bytes_in_use;
   int32_t active_slots, queued;
+  int64_t bypassed;         /* admissions past a head that waited for memory */
 } me_server_stats_t;
 
 /* n_slots HIP streams (1..64), budget_bytes of device memory for requests. */
@@ -277,7 +284,8 @@ me_status me_server_create(int64_t budget_bytes, int32_t n_slots, me_server* out
 
 /* Enqueue a request: h_momenta [nevt][npar][4] and h_out [nevt] are HOST
  * pointers that must stay valid until the ticket completes.  ME_EINVAL for
- * nevt <= 0; ME_ENOMEM if the request alone exceeds the budget.  *ticket
+ * nevt <= 0; ME_ENOMEM if the request's footprint alone exceeds the budget.
+ * *ticket
  * receives an id (monotonic from 1). */
 me_status me_server_submit(me_server s, me_handle h, const double* h_momenta, int64_t nevt,
                            double* h_out, int64_t* ticket);

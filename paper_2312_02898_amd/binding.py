@@ -70,6 +70,7 @@ class me_server_stats_t(ctypes.Structure):
         ("peak_bytes_in_use", ctypes.c_int64),
         ("active_slots", ctypes.c_int32),
         ("queued", ctypes.c_int32),
+        ("bypassed", ctypes.c_int64),
     ]
 
 

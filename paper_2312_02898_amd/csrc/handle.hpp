@@ -31,6 +31,12 @@ inline int mode_of(const me_sm_params& p) {
 // (synchronises the stream); negative on a HIP error.
 int64_t validate_momenta(const double* d_mom, int64_t nevt, int npar, hipStream_t s);
 
+// me_compute with an optional device workspace for the processes that need
+// one (ws == NULL: the stream-ordered allocator; otherwise ws_bytes of it,
+// at least the handle's workspace(mode, nevt, nhel, ws_bytes)).
+me_status compute_on(me_handle h, const double* d_momenta, int64_t nevt, double* d_me, hipStream_t s, void* ws,
+                     int64_t ws_bytes);
+
 // Records code and message for me_last_error(); returns code.
 me_status set_error(me_status code, const std::string& msg);
 

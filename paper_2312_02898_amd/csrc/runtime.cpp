@@ -111,6 +111,30 @@ namespace me {
 
 me_status set_error(me_status code, const std::string& msg) { return fail(code, msg); }
 
+me_status compute_on(me_handle h, const double* d_momenta, int64_t nevt, double* d_me, hipStream_t s, void* ws,
+                     int64_t ws_bytes) {
+  if (!h) return fail(ME_EINVAL, "me_compute: null handle");
+  if (nevt < 0) return fail(ME_EINVAL, "me_compute: nevt < 0");
+  if (nevt == 0) return ME_OK;
+  if (!d_momenta || !d_me) return fail(ME_EINVAL, "me_compute: null pointer");
+  if (h->debug) {
+    const int64_t bad = validate_momenta(d_momenta, nevt, h->proc->npar, s);
+    if (bad < 0) return fail(ME_EHIP, "me_compute: momentum validation failed to run");
+    if (bad > 0)
+      return fail(ME_EINVAL, "me_compute: " + std::to_string(bad) +
+                                 " events with non-finite components, negative energy or unbalanced momentum");
+  }
+  const int rc = h->proc->launch(mode_of(h->params), d_momenta, nevt, d_me, nullptr, &h->kp, s, ws, ws_bytes);
+  if (rc == -3)
+    return fail(ws ? ME_EINVAL : ME_ENOMEM,
+                ws ? "me_compute: workspace too small" : "me_compute: no device memory for the workspace");
+  if (rc != 0) {
+    hipError_t le = hipGetLastError();
+    return fail(ME_EHIP, std::string("me_compute: launch failed: ") + hipGetErrorString(le));
+  }
+  return ME_OK;
+}
+
 me_status compute_channels_on(const me_handle* handles, int32_t nchannels, const double* d_momenta,
                               const int32_t* d_channel, const double* d_alphas, int64_t nevt, double* d_me,
                               hipStream_t s, void* ws, int64_t ws_bytes, const char* who) {
@@ -286,25 +310,7 @@ me_status me_helicity_filter(me_handle h) {
 }
 
 me_status me_compute(me_handle h, const double* d_momenta, int64_t nevt, double* d_me, void* hip_stream) {
-  if (!h) return fail(ME_EINVAL, "me_compute: null handle");
-  if (nevt < 0) return fail(ME_EINVAL, "me_compute: nevt < 0");
-  if (nevt == 0) return ME_OK;
-  if (!d_momenta || !d_me) return fail(ME_EINVAL, "me_compute: null pointer");
-  if (h->debug) {
-    const int64_t bad = me::validate_momenta(d_momenta, nevt, h->proc->npar, static_cast<hipStream_t>(hip_stream));
-    if (bad < 0) return fail(ME_EHIP, "me_compute: momentum validation failed to run");
-    if (bad > 0)
-      return fail(ME_EINVAL, "me_compute: " + std::to_string(bad) +
-                                 " events with non-finite components, negative energy or unbalanced momentum");
-  }
-  int rc = h->proc->launch(me::mode_of(h->params), d_momenta, nevt, d_me, nullptr, &h->kp,
-                           static_cast<hipStream_t>(hip_stream), nullptr, 0);
-  if (rc == -3) return fail(ME_ENOMEM, "me_compute: no device memory for the workspace");
-  if (rc != 0) {
-    hipError_t le = hipGetLastError();
-    return fail(ME_EHIP, std::string("me_compute: launch failed: ") + hipGetErrorString(le));
-  }
-  return ME_OK;
+  return me::compute_on(h, d_momenta, nevt, d_me, static_cast<hipStream_t>(hip_stream), nullptr, 0);
 }
 
 me_status me_workspace_bytes(me_handle h, int64_t nevt, int64_t* bytes) {

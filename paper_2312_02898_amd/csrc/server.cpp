@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "handle.hpp"
 #include "me.h"
 #include "server_core.hpp"
 
@@ -25,6 +26,8 @@ struct HipExec {
   std::vector<int> launch_ok;
 
   static int64_t out_offset(const me::Request& r) { return r.nevt * int64_t(32) * r.npar; }
+  // the request's region: momenta, results, then its process's workspace
+  static int64_t ws_offset(const me::Request& r) { return me::Arena::round(me::ServerCore<HipExec>::io_bytes(r)); }
 
   bool launch(int slot, me::Request& r, int64_t off) {
     (void)hipSetDevice(device);
@@ -33,13 +36,19 @@ struct HipExec {
     std::memcpy(h_arena + off, r.h_mom, in_bytes);
     double* d_mom = reinterpret_cast<double*>(d_arena + off);
     double* d_out = reinterpret_cast<double*>(d_arena + off + out_offset(r));
+    void* d_ws = r.ws_bytes > 0 ? d_arena + off + ws_offset(r) : nullptr;
     hipStream_t s = streams[slot];
-    if (hipMemcpyAsync(d_mom, h_arena + off, in_bytes, hipMemcpyHostToDevice, s) != hipSuccess) return false;
-    if (me_compute(static_cast<me_handle>(r.handle), d_mom, r.nevt, d_out, s) != ME_OK) return false;
-    if (hipMemcpyAsync(h_arena + off + out_offset(r), d_out, size_t(r.nevt) * 8, hipMemcpyDeviceToHost, s) !=
-        hipSuccess)
+    bool ok = hipMemcpyAsync(d_mom, h_arena + off, in_bytes, hipMemcpyHostToDevice, s) == hipSuccess;
+    ok = ok && me::compute_on(static_cast<me_handle>(r.handle), d_mom, r.nevt, d_out, s, d_ws, r.ws_bytes) == ME_OK;
+    ok = ok && hipMemcpyAsync(h_arena + off + out_offset(r), d_out, size_t(r.nevt) * 8, hipMemcpyDeviceToHost,
+                              s) == hipSuccess;
+    ok = ok && hipEventRecord(events[slot], s) == hipSuccess;
+    if (!ok) {
+      // the core frees the region at once: nothing queued above may still
+      // be reading or writing it
+      (void)hipStreamSynchronize(s);
       return false;
-    if (hipEventRecord(events[slot], s) != hipSuccess) return false;
+    }
     launch_ok[slot] = 1;
     return true;
   }
@@ -57,8 +66,14 @@ struct HipExec {
 
 }  // namespace
 
+// Workspace cap per request: a quarter of the budget, at most 256 MiB (the
+// split form then runs its helicities in several passes over a smaller
+// workspace; a request needs at least one helicity slot of it).
+constexpr int64_t kServeWorkspaceCap = int64_t(256) << 20;
+
 struct me_server_s {
   HipExec exec;
+  int64_t ws_cap = 0;
   std::unique_ptr<me::ServerCore<HipExec>> core;
 };
 
@@ -89,6 +104,7 @@ me_status me_server_create(int64_t budget_bytes, int32_t n_slots, me_server* out
     delete s;
     return ME_EHIP;
   }
+  s->ws_cap = budget_bytes / 4 < kServeWorkspaceCap ? budget_bytes / 4 : kServeWorkspaceCap;
   s->core.reset(new me::ServerCore<HipExec>(ex, budget_bytes, n_slots));
   *out = s;
   return ME_OK;
@@ -105,6 +121,8 @@ me_status me_server_submit(me_server s, me_handle h, const double* h_momenta, in
   r.h_out = h_out;
   r.nevt = nevt;
   r.npar = info.npar;
+  // the device workspace of the request's process counts in its footprint
+  r.ws_bytes = nevt > 0 ? h->proc->workspace(me::mode_of(h->params), nevt, h->kp.nhel, s->ws_cap) : 0;
   int rc = s->core->submit(r, ticket);
   if (rc == -1) return ME_EINVAL;
   if (rc == -3) return ME_ENOMEM;
@@ -155,6 +173,7 @@ me_status me_server_stats(me_server s, me_server_stats_t* st) {
   st->peak_bytes_in_use = x.peak_bytes_in_use;
   st->active_slots = x.active_slots;
   st->queued = x.queued;
+  st->bypassed = x.bypassed;
   return ME_OK;
 }
 

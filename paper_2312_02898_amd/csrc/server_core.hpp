@@ -2,15 +2,22 @@
 // footprint and a fixed number of execution slots (continuous batching of
 // uneven |M|^2 requests from several processes).
 //
-// Requests are admitted strictly in arrival order (no starvation): the head
-// of the queue is admitted as soon as a slot is free and the arena can hold
-// its footprint; requests admitted while others are in flight run
-// concurrently on their own slots.  The executor does the device work; the
-// core only does bookkeeping, so it is independent of HIP and can be driven by
-// a fake executor on the CPU.
+// A request's footprint is everything its device work touches: momenta,
+// results and the workspace its process needs (the split form's jamp
+// workspace), all carved from one arena of the server's budget.  Requests
+// are admitted in arrival order as soon as a slot is free and the arena can
+// hold the head's footprint.  When the head does not fit (it waits for
+// memory, not for a slot), later requests that fit may pass it, but at most
+// max_bypass of them per head: after that the queue is strictly in order
+// until the head is admitted, so the head's wait is bounded by the service
+// of the work already admitted.  Requests admitted while others are in
+// flight run concurrently on their own slots.  The executor does the device
+// work; the core only does bookkeeping, so it is independent of HIP and can
+// be driven by a fake executor on the CPU.
 //
 //   struct Executor {
-//     // start the request's work on `slot`; false on launch failure
+//     // start the request's work on `slot`; false on launch failure, and
+//     // then nothing of the request may still be in flight on the slot
 //     bool launch(int slot, Request& r, int64_t offset);
 //     // non-blocking completion test of the work on `slot`
 //     bool done(int slot);
@@ -37,7 +44,8 @@ struct Request {
   double* h_out = nullptr;         // host output [nevt]
   int64_t nevt = 0;
   int32_t npar = 0;
-  int64_t bytes = 0;               // device footprint
+  int64_t ws_bytes = 0;            // device workspace of the request's process (set by the submitter)
+  int64_t bytes = 0;               // device footprint: momenta, results and workspace
   std::chrono::steady_clock::time_point t_submit;
   std::chrono::steady_clock::time_point t_admit;   // slot and memory granted, work launched
 };
@@ -95,6 +103,7 @@ class Arena {
 
 struct ServerStats {
   int64_t submitted = 0, completed = 0, failed = 0, rejected = 0, events_completed = 0;
+  int64_t bypassed = 0;   // admissions past a head that waited for memory
   int64_t bytes_in_use = 0, peak_bytes_in_use = 0;
   int32_t active_slots = 0, queued = 0;
 };
@@ -102,16 +111,20 @@ struct ServerStats {
 template <class Exec>
 class ServerCore {
  public:
-  ServerCore(Exec& ex, int64_t budget, int nslots)
-      : ex_(ex), arena_(budget), slots_(nslots), stop_(false) {
+  // momenta [nevt][npar][4] and results [nevt] precede the workspace in a
+  // request's region
+  static int64_t io_bytes(const Request& r) { return r.nevt * (int64_t(32) * r.npar + 8); }
+
+  ServerCore(Exec& ex, int64_t budget, int nslots, int max_bypass = 16)
+      : ex_(ex), arena_(budget), slots_(nslots), max_bypass_(max_bypass), stop_(false) {
     loop_ = std::thread([this] { run(); });
   }
   ~ServerCore() { shutdown(); }
 
   // 0 on success; -1 invalid, -3 larger than the whole budget.
   int submit(Request r, int64_t* ticket) {
-    if (r.nevt <= 0 || !r.h_mom || !r.h_out || r.npar <= 0) return -1;
-    r.bytes = Arena::round(r.nevt * (int64_t(32) * r.npar + 8));
+    if (r.nevt <= 0 || !r.h_mom || !r.h_out || r.npar <= 0 || r.ws_bytes < 0) return -1;
+    r.bytes = Arena::round(Arena::round(io_bytes(r)) + r.ws_bytes);
     std::lock_guard<std::mutex> lk(mu_);
     if (r.bytes > arena_.capacity()) {
       ++st_.rejected;
@@ -212,12 +225,26 @@ class ServerCore {
       for (size_t i = 0; i < slots_.size(); ++i)
         if (!slots_[i].busy) { free_slot = int(i); break; }
       if (free_slot < 0) break;
+      // the head if it fits; else, while the head may still be passed, the
+      // first later request that fits
+      size_t pick = 0;
       int64_t off = arena_.alloc(queue_.front().bytes);
-      if (off < 0) break;   // head-of-line: wait for memory, keep arrival order
+      if (off < 0) {
+        if (head_bypassed_ >= max_bypass_) break;   // strictly in order until the head is admitted
+        for (size_t q = 1; q < queue_.size() && q <= kBypassWindow; ++q) {
+          off = arena_.alloc(queue_[q].bytes);
+          if (off >= 0) { pick = q; break; }
+        }
+        if (off < 0) break;
+        ++head_bypassed_;
+        ++st_.bypassed;
+      } else {
+        head_bypassed_ = 0;
+      }
       Slot& s = slots_[free_slot];
-      s.req = queue_.front();
+      s.req = queue_[pick];
       s.req.t_admit = std::chrono::steady_clock::now();
-      queue_.pop_front();
+      queue_.erase(queue_.begin() + std::ptrdiff_t(pick));
       s.busy = true;
       s.off = off;
       st_.peak_bytes_in_use = std::max(st_.peak_bytes_in_use, arena_.used());
@@ -261,9 +288,14 @@ class ServerCore {
     }
   }
 
+  // later requests looked at when the head does not fit
+  static constexpr size_t kBypassWindow = 64;
+
   Exec& ex_;
   Arena arena_;
   std::vector<Slot> slots_;
+  int max_bypass_;
+  int head_bypassed_ = 0;   // requests admitted past the current head
   std::deque<Request> queue_;
   std::map<int64_t, TicketState> tickets_;
   ServerStats st_;

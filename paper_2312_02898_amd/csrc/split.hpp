@@ -98,12 +98,16 @@ struct SplitTiles {
 // Mixed form: jamps (FP32) split into FP16 hi + lo after a per-event
 // power-of-two scale, colour matrix exact in FP16, FP32 accumulation on
 // v_mfma_f32_16x16x32_f16; helicity sum in FP64.
-// Block: 4 waves, 16 events per wave.  out[e] = (accumulate ? out[e] : 0) +
-// sum over the chunk's helicities of q_h * g^2n / (CDEN * IDEN).
+// Block: 4 waves, 16 events per wave.  The helicity sum runs over passes
+// (helicity slices of the workspace) in helicity order, one addition per
+// helicity, so its rounding does not depend on how the helicities are
+// sliced: the first pass starts from 0, later ones from out[e], which holds
+// the unscaled partial sum; the last pass stores the sum times
+// g^2n / (CDEN * IDEN).
 template <class P>
 __global__ __launch_bounds__(256) void me_colour_split_f16(const cx<float>* __restrict__ X, int64_t ne,
                                                            int64_t ne_pad, int nh, double* __restrict__ out,
-                                                           int accumulate, const MeParams prm) {
+                                                           int first, int last, const MeParams prm) {
   constexpr int NC = P::NCOLOR;
   using TL = SplitTiles<NC>;
   const int lane = threadIdx.x % 64, n = lane % 16, g = lane / 16;
@@ -122,7 +126,7 @@ __global__ __launch_bounds__(256) void me_colour_split_f16(const cx<float>* __re
         const int row = 16 * mt + n, col = 16 * (2 * s + j / 4) + 4 * g + j % 4;
         A[mt][s][j] = (row < NC && col < NC) ? _Float16(float(cm[row * NC + col])) : _Float16(0.0f);
       }
-  double acc = 0.0;
+  double acc = (!first && live && g == 0) ? out[e] : 0.0;
   for (int hc = 0; hc < nh; ++hc) {
     // this lane's colours 16 mt + 4 g + i of event e
     float xr[TL::MT2][4], xi[TL::MT2][4];
@@ -179,10 +183,7 @@ __global__ __launch_bounds__(256) void me_colour_split_f16(const cx<float>* __re
     q += __shfl_xor(q, 32, 64);
     acc += double(ldexpf(q, 2 * ex));
   }
-  if (live && g == 0) {
-    const double f = P::coupling_factor(prm) / (P::CDEN * P::IDEN);
-    out[e] = (accumulate ? out[e] : 0.0) + acc * f;
-  }
+  if (live && g == 0) out[e] = last ? acc * (P::coupling_factor(prm) / (P::CDEN * P::IDEN)) : acc;
 }
 
 // FP64 form on v_mfma_f64_16x16x4_f64.  Its result rows are interleaved:
@@ -191,12 +192,13 @@ __global__ __launch_bounds__(256) void me_colour_split_f16(const cx<float>* __re
 // step s holds colour kappa(s, g) = 16 (s/4) + g + 4 (s%4).  The colour
 // matrix sits in LDS as FP32 (exact integers), converted per step.  out_hel
 // (optional) receives the colour-summed |M_h|^2 of every helicity,
-// [nevt][NHEL].
+// [nevt][NHEL].  The helicity sum over passes is accumulated as in the FP16
+// form (first, last: see there).
 template <class P>
 __global__ __launch_bounds__(256) void me_colour_split_f64(const cx<double>* __restrict__ X, int64_t ne,
                                                            int64_t ne_pad, int nh, int h0,
                                                            double* __restrict__ out, double* __restrict__ out_hel,
-                                                           int accumulate, const MeParams prm) {
+                                                           int first, int last, const MeParams prm) {
   constexpr int NC = P::NCOLOR;
   using TL = SplitTiles<NC>;
   constexpr int LDW = TL::NCP + 1;
@@ -212,7 +214,7 @@ __global__ __launch_bounds__(256) void me_colour_split_f64(const cx<double>* __r
   if (e - n >= ne) return;   // whole wave past the end (wave-uniform)
   const bool live = e < ne;
   const double f = P::coupling_factor(prm) / P::CDEN;
-  double acc = 0.0;
+  double acc = (!first && out && live && g == 0) ? out[e] : 0.0;
   for (int hc = 0; hc < nh; ++hc) {
     const cx<double>* xrow = X + int64_t(hc) * NC * ne_pad + e;
     double q = 0.0;
@@ -247,7 +249,7 @@ __global__ __launch_bounds__(256) void me_colour_split_f64(const cx<double>* __r
     if (out_hel && live && g == 0) out_hel[e * P::NHEL + prm.hel[h0 + hc]] = q * f;
     acc += q;
   }
-  if (out && live && g == 0) out[e] = (accumulate ? out[e] : 0.0) + acc * (f / P::IDEN);
+  if (out && live && g == 0) out[e] = last ? acc * (f / P::IDEN) : acc;
 }
 
 // Events per chunk and the default workspace cap per call.  Without a
@@ -303,13 +305,13 @@ int run_split(const double* mom, int64_t nevt, double* out, double* out_hel, con
           parts[j](dim3(unsigned((ne + 255) / 256), unsigned(nhc)), stream, mom + e0 * 4 * P::NPAR, ne, h0, X,
                    ne_pad, &prm);
       const dim3 cgrid(unsigned((ne + 63) / 64));
+      const int first = h0 == 0 ? 1 : 0, last = h0 + nhc >= prm.nhel ? 1 : 0;
       if constexpr (sizeof(T) == 8)
         hipLaunchKernelGGL((me_colour_split_f64<P>), cgrid, dim3(256), 0, stream, X, ne, ne_pad, nhc, h0,
-                           out ? out + e0 : nullptr, out_hel ? out_hel + e0 * P::NHEL : nullptr, h0 > 0 ? 1 : 0,
-                           prm);
+                           out ? out + e0 : nullptr, out_hel ? out_hel + e0 * P::NHEL : nullptr, first, last, prm);
       else
         hipLaunchKernelGGL((me_colour_split_f16<P>), cgrid, dim3(256), 0, stream, X, ne, ne_pad, nhc, out + e0,
-                           h0 > 0 ? 1 : 0, prm);
+                           first, last, prm);
     }
   }
   const hipError_t err = hipGetLastError();

@@ -33,11 +33,15 @@ def make_stream(names, nreq, rate_hz, seed=5, nmin=256, nmax=65536):
     return arrivals, procs, moms
 
 
-def run_stream(handles, arrivals, procs, moms, budget_bytes=1 << 30, n_slots=8, timeout_s=120.0, times=None):
+def run_stream(handles, arrivals, procs, moms, budget_bytes=1 << 30, n_slots=8, timeout_s=120.0, times=None,
+               on_created=None):
     """Replay the stream against a server; returns per-request latencies,
     outputs and the wall time.  If `times` is a list, it receives the
-    (queue_s, service_s) split of every request."""
+    (queue_s, service_s) split of every request; on_created(server) runs
+    once the server exists, before the first submission."""
     srv = B.me_server_create(budget_bytes, n_slots)
+    if on_created is not None:
+        on_created(srv)
     outs = [np.empty(m.shape[0], dtype=np.float64) for m in moms]
     tickets = []
     t0 = time.perf_counter()

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "server_core.hpp"
@@ -15,6 +16,7 @@ using clk = std::chrono::steady_clock;
 
 struct FakeExec {
   double service_s = 0.01;
+  std::vector<double> service_of;   // per ticket (index ticket - 1), overrides service_s
   int fail_launch_ticket = -1, fail_finish_ticket = -1;
   std::vector<clk::time_point> t0;
   std::vector<int64_t> slot_ticket;
@@ -36,7 +38,9 @@ struct FakeExec {
     return true;
   }
   bool done(int slot) {
-    return std::chrono::duration<double>(clk::now() - t0[slot]).count() >= service_s;
+    const int64_t t = slot_ticket[slot];
+    const double sv = t >= 1 && size_t(t) <= service_of.size() ? service_of[t - 1] : service_s;
+    return std::chrono::duration<double>(clk::now() - t0[slot]).count() >= sv;
   }
   bool finish(int slot, me::Request& r, int64_t) {
     std::lock_guard<std::mutex> lk(mu);
@@ -48,8 +52,73 @@ struct FakeExec {
   }
 };
 
+// Requests with a device workspace, and a head that waits for memory.
+//   "workspace": 12 requests of 1000 events (136 000 B of momenta and
+//   results) plus 300 000 B of workspace each, 1 MiB budget, 8 slots: the
+//   footprint with the workspace limits concurrency to two.
+//   "bypass": three 400 kB requests (80 ms), then one of 900 kB that must
+//   wait for all of them, then 40 small ones (40 kB, 5 ms): small ones pass
+//   the waiting head at most max_bypass = 16 times, then the queue is in
+//   order until the big one is admitted.
+int run_footprint(const std::string& sc) {
+  const int nslots = 8;
+  const int64_t budget = 1 << 20;
+  FakeExec ex(nslots);
+  std::vector<int64_t> nevts, wss;
+  if (sc == "workspace") {
+    for (int i = 0; i < 12; ++i) { nevts.push_back(1000); wss.push_back(300000); ex.service_of.push_back(0.02); }
+  } else {
+    for (int i = 0; i < 3; ++i) { nevts.push_back(2000); wss.push_back(128000); ex.service_of.push_back(0.08); }
+    nevts.push_back(1000); wss.push_back(764000); ex.service_of.push_back(0.01);
+    for (int i = 0; i < 40; ++i) { nevts.push_back(100); wss.push_back(26000); ex.service_of.push_back(0.005); }
+  }
+  const int nreq = int(nevts.size());
+  std::vector<std::vector<double>> in(nreq), out(nreq);
+  std::vector<int64_t> tickets;
+  std::vector<double> queue(nreq);
+  std::vector<int> status(nreq);
+  me::ServerStats st;
+  {
+    me::ServerCore<FakeExec> core(ex, budget, nslots);
+    for (int i = 0; i < nreq; ++i) {
+      in[i].assign(nevts[i] * 16, 0.0);
+      for (int64_t e = 0; e < nevts[i]; ++e) in[i][e * 16] = double(i * 100000 + e);
+      out[i].assign(nevts[i], -1.0);
+      me::Request r;
+      r.h_mom = in[i].data(); r.h_out = out[i].data(); r.nevt = nevts[i]; r.npar = 4; r.ws_bytes = wss[i];
+      int64_t t = -1;
+      if (core.submit(r, &t) != 0) return 2;
+      tickets.push_back(t);
+      if (sc == "bypass" && i == 2) std::this_thread::sleep_for(std::chrono::milliseconds(5));
+    }
+    for (int i = 0; i < nreq; ++i) {
+      me::TicketState ts; bool known;
+      bool ok = core.wait(tickets[i], 30.0, &ts, &known);
+      status[i] = ok ? ts.status : 999;
+      queue[i] = ts.queue_s;
+    }
+    st = core.stats();
+  }
+  int correct = 1;
+  for (int i = 0; i < nreq; ++i)
+    for (size_t e = 0; e < out[i].size(); ++e)
+      if (out[i][e] != 2.0 * in[i][e * 16]) correct = 0;
+  printf("{\"scenario\": \"%s\", \"correct\": %d, \"completed\": %lld, \"failed\": %lld, \"bypassed\": %lld,"
+         " \"peak_bytes\": %lld, \"bytes_in_use\": %lld, \"budget\": %lld, \"max_concurrent\": %d, \"status\": [",
+         sc.c_str(), correct, (long long)st.completed, (long long)st.failed, (long long)st.bypassed,
+         (long long)st.peak_bytes_in_use, (long long)st.bytes_in_use, (long long)budget, ex.max_concurrent.load());
+  for (int i = 0; i < nreq; ++i) printf("%s%d", i ? ", " : "", status[i]);
+  printf("], \"queue\": [");
+  for (int i = 0; i < nreq; ++i) printf("%s%.6f", i ? ", " : "", queue[i]);
+  printf("], \"admit_order\": [");
+  for (size_t i = 0; i < ex.admit_order.size(); ++i) printf("%s%lld", i ? ", " : "", (long long)ex.admit_order[i]);
+  printf("]}\n");
+  return 0;
+}
+
 int main(int argc, char** argv) {
   std::string sc = argc > 1 ? argv[1] : "basic";
+  if (sc == "workspace" || sc == "bypass") return run_footprint(sc);
   int nslots = sc == "memory" ? 8 : 4;
   int64_t budget = sc == "memory" ? 300000 : (1 << 20);   // "memory": about 2 requests fit
   int nreq = sc == "overlap" ? 8 : 12;

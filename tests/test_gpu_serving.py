@@ -1,8 +1,10 @@
 """Serving form on the GPU: requests of several processes and uneven sizes
 arrive while others run; every result equals the same request evaluated
 alone (bit for bit: events are independent and each lane's arithmetic does
-not depend on its neighbours), memory admission holds the budget, and a
-request larger than the whole budget is rejected."""
+not depend on its neighbours), memory admission holds the budget with each
+request's workspace counted in its footprint (free device memory does not
+move while a g g > t t~ g g g heavy stream runs), and a request larger than
+the whole budget is rejected."""
 import numpy as np
 import pytest
 
@@ -37,7 +39,7 @@ def _alone(B, h, mom):
     return out.cpu().numpy()
 
 
-@pytest.mark.parametrize("budget,slots", [(1 << 30, 8), (6 << 20, 4)])
+@pytest.mark.parametrize("budget,slots", [(1 << 30, 8), (64 << 20, 4)])
 def test_mix_equals_alone(handles, budget, slots):
     from paper_2312_02898_amd import binding as B
     from paper_2312_02898_amd.serving import make_stream, run_stream
@@ -57,6 +59,50 @@ def test_mix_equals_alone(handles, budget, slots):
         assert np.array_equal(o, ref), name
     print(f"  p50 {np.median(lat) * 1e3:.2f} ms p99 {np.quantile(lat, 0.99) * 1e3:.2f} ms wall {wall:.3f} s",
           flush=True)
+
+
+def test_workspace_inside_the_budget(handles):
+    """g g > t t~ g g g requests carry their jamp workspace in their
+    footprint: the server's arena (allocated at creation) is all the device
+    memory the stream uses, so free memory sampled while it runs never drops
+    below its value after creation, and peak arena use stays within the
+    budget, with the budget small enough that admission waits for memory."""
+    import threading
+    from paper_2312_02898_amd import binding as B
+    from paper_2312_02898_amd.serving import make_stream, run_stream
+    budget = 96 << 20
+    names = ["ggttggg", "ggttgg", "ggttggg"]
+    arr, procs, moms = make_stream(names, 24, rate_hz=5000.0, seed=9, nmin=256, nmax=12000)
+    ws = {nm: B.me_workspace_bytes(handles[nm], 12000) for nm in ("ggttgg", "ggttggg")}
+    assert ws["ggttgg"] == 0 and ws["ggttggg"] > 0
+    print(f"[serving workspace] budget={budget} requests={len(procs)}", flush=True)
+    torch.cuda.synchronize()
+    base, samples, stop = [], [], threading.Event()
+
+    def created(_srv):
+        torch.cuda.synchronize()
+        base.append(torch.cuda.mem_get_info()[0])
+
+    def poll():
+        while not stop.is_set():
+            samples.append(torch.cuda.mem_get_info()[0])
+            stop.wait(0.0005)
+    th = threading.Thread(target=poll)
+    th.start()
+    try:
+        lat, status, outs, wall, st = run_stream(handles, arr, procs, moms, budget_bytes=budget, n_slots=8,
+                                                 on_created=created)
+    finally:
+        stop.set()
+        th.join()
+    assert (status == 0).all() and st["completed"] == len(procs)
+    assert st["peak_bytes_in_use"] <= budget
+    during = samples
+    print(f"  free after creation {base[0] / 2**20:.1f} MiB, lowest while serving {min(during) / 2**20:.1f} MiB, "
+          f"peak arena {st['peak_bytes_in_use'] / 2**20:.1f} MiB, passes {st['bypassed']}", flush=True)
+    assert min(during) >= base[0] - (2 << 20)
+    for name, m, o in zip(procs, moms, outs):
+        assert np.array_equal(o, _alone(B, handles[name], m)), name
 
 
 def test_over_budget_and_invalid(handles):

@@ -1,6 +1,7 @@
 """Serving core on the CPU with a fake executor (synthetic service times,
-injected failures): admission by memory footprint, arrival-order admission
-without starvation, overlap of admitted work, failure isolation and
+injected failures): admission by memory footprint (momenta, results and
+workspace), arrival-order admission with bounded passing of a head that
+waits for memory, overlap of admitted work, failure isolation and
 consistent accounting."""
 import json
 import os
@@ -68,3 +69,34 @@ def test_failure_isolation(harness):
     assert all(s == 0 for i, s in enumerate(st) if i not in (2, 6))
     assert r["failed"] == 2 and r["completed"] == 10
     assert r["bytes_in_use"] == 0
+
+
+def test_workspace_counts_in_the_footprint(harness):
+    """Each request needs 136 kB of momenta and results plus 300 kB of
+    workspace: with a 1 MiB budget and eight slots only two run at once,
+    the arena never holds more than the budget, and all complete."""
+    r = run(harness, "workspace")
+    assert r["completed"] == 12 and r["correct"] == 1 and r["failed"] == 0
+    assert r["peak_bytes"] <= r["budget"]
+    assert r["max_concurrent"] == 2
+    assert r["bytes_in_use"] == 0
+
+
+def test_small_requests_pass_a_waiting_head_boundedly(harness):
+    """Three 400 kB requests (two fit the 1 MiB budget at once), a 900 kB one
+    that must wait for all of them, then 40 small ones: while a head waits
+    for memory, small requests behind it pass it, at most 16 times per head,
+    after which the queue is in order until that head is admitted; nothing
+    starves and every pass is counted."""
+    r = run(harness, "bypass")
+    assert r["completed"] == 44 and r["correct"] == 1 and r["failed"] == 0
+    assert r["peak_bytes"] <= r["budget"]
+    order = r["admit_order"]
+    # the two heads that waited (tickets 3 and 4) were each passed, boundedly
+    n3 = len([u for u in order[:order.index(3)] if u > 3])
+    n4 = len([u for u in order[:order.index(4)] if u > 4 and order.index(u) > order.index(3)])
+    assert 1 <= n3 <= 16 and 1 <= n4 <= 16
+    assert r["bypassed"] == n3 + n4
+    # small requests that passed were taken in arrival order
+    small = [t for t in order if t > 4]
+    assert small == sorted(small)
