@@ -130,6 +130,13 @@ __device__ __forceinline__ double lc_plus(const double* p, double m2) {
 __device__ __forceinline__ double lc_minus(const double* p, double m2) {
   return p[3] <= 0 ? p[0] - p[3] : (m2 + p[1] * p[1] + p[2] * p[2]) / (p[0] + p[3]);
 }
+// The small one of E +- pz, (m^2 + pT^2) / (E + |pz|), and the light-cone
+// components from it (s: the small component, from a per-event cache).
+__device__ __forceinline__ double lc_small(const double* p, double m2) {
+  return (m2 + p[1] * p[1] + p[2] * p[2]) / (p[0] + fabs(p[3]));
+}
+__device__ __forceinline__ double lc_plus_s(const double* p, double s) { return p[3] >= 0 ? p[0] + p[3] : s; }
+__device__ __forceinline__ double lc_minus_s(const double* p, double s) { return p[3] <= 0 ? p[0] - p[3] : s; }
 // (a + b)^2 = 2 a.b for two massless on-shell momenta, as
 // |E_b a_vec - E_a b_vec|^2 / (E_a E_b): the difference vector is small when
 // the two are nearly collinear and is formed with one rounding per component,
@@ -480,6 +487,9 @@ template <class J> __device__ __forceinline__ void hold_jamp(J&, int) {}
 // forms them in place from the momenta otherwise (this type).
 struct NoKinCache {
   static constexpr bool kCached = false;
+  static constexpr bool kLc = false;   // no light-cone cache either
+  __device__ __forceinline__ double lcs(int) const { return 0.0; }
+  __device__ __forceinline__ double pair(int) const { return 0.0; }
 };
 
 // A momentum copy the compiler cannot identify with the original, for

@@ -65,6 +65,9 @@ __global__ __launch_bounds__(256) void me_kernel(const double* __restrict__ mom,
 template <class T>
 struct LdsKinCache {
   static constexpr bool kCached = true;
+  static constexpr bool kLc = false;   // cached factors already hold the light-cone forms
+  __device__ __forceinline__ double lcs(int) const { return 0.0; }
+  __device__ __forceinline__ double pair(int) const { return 0.0; }
   T* re;
   cx<T>* cxs;
   T* eb;
@@ -140,6 +143,24 @@ __global__ __launch_bounds__(256) void me_kernel_kc(const double* __restrict__ m
   if (out) out[e] = acc * (P::coupling_factor(prm) / (P::CDEN * P::IDEN));
 }
 
+// Per-event light-cone cache of the FP64 form in LDS (128-thread blocks):
+// the small light-cone component of each outgoing leg and the invariants of
+// the pairs of massless outgoing legs, formed once per event and read where
+// the propagator invariants are formed (slot s of thread t at s * 128 + t).
+// The per-iteration offset passes through an empty asm statement so that the
+// reads stay inside the helicity loop instead of being held in registers.
+struct LdsLcCache {
+  static constexpr bool kCached = false;
+  static constexpr bool kLc = true;
+  double* base;
+  int npair0;   // first pair slot (after the legs)
+  int off;
+  __device__ __forceinline__ double lcs(int k) const { return base[k * 128 + off]; }
+  __device__ __forceinline__ double pair(int k) const { return base[(npair0 + k) * 128 + off]; }
+  __device__ __forceinline__ void set_lcs(int k, double v) { base[k * 128 + off] = v; }
+  __device__ __forceinline__ void set_pair(int k, double v) { base[(npair0 + k) * 128 + off] = v; }
+};
+
 // Jamps of one lane held in LDS instead of registers: element k of lane l at
 // base[k * 64 + l], so a wave's 64 accesses to one jamp are contiguous.
 template <class T>
@@ -155,12 +176,17 @@ __global__ __launch_bounds__(128) void me_kernel_ldsjamp(const double* __restric
                                                           double* __restrict__ out, double* __restrict__ out_hel,
                                                           const MeParams prm) {
   __shared__ cx<T> lds[2 * P::NCOLOR * 64];
+  // the light-cone cache of the FP64 form (its light-cone invariants)
+  constexpr int NLC = sizeof(T) == 8 ? P::LC_LEGS + P::LC_PAIRS : 1;
+  __shared__ double lcb[NLC * 128];
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= nevt) return;
   LdsJamps<T> jamp{lds + wave * P::NCOLOR * 64 + lane};
   double p[P::NPAR][4];
   load_on_shell<P::MASSIVE>(mom + e * (4 * P::NPAR), p, prm.mt);
+  LdsLcCache lc{lcb, P::LC_LEGS, int(threadIdx.x)};
+  if constexpr (sizeof(T) == 8) P::lc_fill(p, prm, lc);
   double acc = 0.0;
   for (int ih = 0; ih < prm.nhel; ++ih) {
 #pragma unroll
@@ -168,7 +194,12 @@ __global__ __launch_bounds__(128) void me_kernel_ldsjamp(const double* __restric
 #pragma unroll
       for (int c = 0; c < 4; ++c) asm volatile("" : "+v"(p[i][c]));
     const unsigned hel = prm.hel[ih];
-    P::template amplitudes<T>(p, hel, prm, jamp);
+    if constexpr (sizeof(T) == 8) {
+      asm volatile("" : "+v"(lc.off));
+      P::template amplitudes<T>(p, hel, prm, jamp, lc);
+    } else {
+      P::template amplitudes<T>(p, hel, prm, jamp);
+    }
     const double q = double(P::template colour_sum<T>(jamp));
     if (out_hel) out_hel[e * P::NHEL + hel] = q * (P::coupling_factor(prm) / P::CDEN);
     acc += q;

@@ -67,8 +67,22 @@ template <int J, class Q = P> void parts(const double (&p)[P::NPAR][4], unsigned
   if constexpr (J < N) { Q::template part<T, J>(p, h, prm, X, 1, qb); parts<J + 1, Q>(p, h, prm, X); }
 }
 // stands in for the kernel's per-event LDS cache of propagator factors
+// stands in for the FP64 kernel's per-event light-cone cache
+struct HostLcCache {
+  static constexpr bool kCached = false;
+  static constexpr bool kLc = true;
+  double v[64];
+  int npair0;
+  double lcs(int k) const { return v[k]; }
+  double pair(int k) const { return v[npair0 + k]; }
+  void set_lcs(int k, double x) { v[k] = x; }
+  void set_pair(int k, double x) { v[npair0 + k] = x; }
+};
 template <class T> struct HostKinCache {
   static constexpr bool kCached = true;
+  static constexpr bool kLc = false;
+  double lcs(int) const { return 0.0; }
+  double pair(int) const { return 0.0; }
   T re[64];
   cx<T> cxs[64];
   T r(int s) const { return re[s]; }
@@ -95,6 +109,13 @@ void jamps(const double (&p)[Q::NPAR][4], unsigned h, const MeParams& prm, cx<T>
     for (int s = 0; s < 16; ++s) for (int c = 0; c < 5; ++c) dc.eb[s][c] = T(1e30);
     Q::template den_fill_f64<T>(p, prm, dc);
     Q::template amplitudes_f64<T>(p, h, prm, J, dc);
+  } else if constexpr (sizeof(T) == 8 && Q::FP64_LDS_JAMPS) {
+    // the FP64 kernel with LDS jamps reads its light-cone invariants from a cache
+    HostLcCache lc;
+    lc.npair0 = Q::LC_LEGS;
+    for (int s = 0; s < 64; ++s) lc.v[s] = 1e30;
+    Q::lc_fill(p, prm, lc);
+    Q::template amplitudes_f64<T>(p, h, prm, J, lc);
   } else if constexpr (sizeof(T) == 8) {
     Q::template amplitudes_f64<T>(p, h, prm, J);
   } else if constexpr (Q::KC_RE_F32 + Q::KC_CX_F32 + Q::KC_EPS_F32 > 0) {
