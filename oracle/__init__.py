@@ -113,6 +113,9 @@ def proc_id(process) -> int:
 
 
 def npar(process) -> int:
+    if _general(process):
+        from . import feyn
+        return feyn.process(process).n
     return lib().oracle_npar(proc_id(process))
 
 
@@ -121,13 +124,25 @@ def ncolor(process) -> int:
 
 
 def iden(process) -> float:
+    if _general(process):
+        from . import feyn
+        return float(feyn.process(process).iden)
     return lib().oracle_iden(proc_id(process))
+
+
+def _general(process) -> bool:
+    """Processes of the diagram-by-diagram evaluation (feyn.py): every QCD
+    process the C++ oracle does not cover."""
+    return isinstance(process, str) and process not in PROCESSES
 
 
 def me(process, mom, params: Params | None = None, long_double=False, nthreads=0):
     """Averaged |M|^2 per event; mom is float64 [nevt][npar][4]."""
     p = params or default_params()
     mom = np.ascontiguousarray(mom, dtype=np.float64)
+    if _general(process):
+        from . import feyn
+        return feyn.me(process, mom, p, long_double=long_double)
     out = np.empty(mom.shape[0], dtype=np.float64)
     rc = lib().oracle_me(proc_id(process), ctypes.byref(p), _dp(mom), mom.shape[0], _dp(out),
                          int(long_double), int(nthreads))
@@ -140,6 +155,9 @@ def me_hel(process, mom, params: Params | None = None, nthreads=0):
     """Colour-summed (not averaged) |M_h|^2, shape [nevt][2^npar]."""
     p = params or default_params()
     mom = np.ascontiguousarray(mom, dtype=np.float64)
+    if _general(process):
+        from . import feyn
+        return feyn.me(process, mom, p, per_helicity=True)
     n = npar(process)
     out = np.empty((mom.shape[0], 1 << n), dtype=np.float64)
     rc = lib().oracle_me_hel(proc_id(process), ctypes.byref(p), _dp(mom), mom.shape[0], _dp(out),

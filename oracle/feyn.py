@@ -1,0 +1,500 @@
+"""Tree-level QCD |M|^2 from its Feynman diagrams -- TEST INFRASTRUCTURE ONLY.
+
+The plain definition (the quantity the paper's Sec. 2 evaluates per event):
+
+    |M|^2 = 1/IDEN  sum_helicities  sum_colours  | sum_diagrams M_d |^2
+
+for any process of gluons, light quarks (u, d; massless) and top quarks with
+the QCD Feynman rules of the C++ oracle (Peskin-Schroeder, all vertex
+momenta incoming):
+    q qbar g : +i g gamma^mu t^a
+    g g g    : g f^{abc} [g^{mu nu}(k-p)^rho + g^{nu rho}(p-q)^mu + g^{rho mu}(q-k)^nu]
+    g g g g  : -i g^2 [f^{abe}f^{cde}(g^{mu rho}g^{nu sigma} - g^{mu sigma}g^{nu rho})
+                       + f^{ace}f^{bde}(g^{mu nu}g^{rho sigma} - g^{mu sigma}g^{nu rho})
+                       + f^{ade}f^{bce}(g^{mu nu}g^{rho sigma} - g^{mu rho}g^{nu sigma})]
+    fermion propagator i(p-slash + m)/(p^2 - m^2 + i m Gamma), gluon -i g_{mu nu}/p^2,
+and the widths of the C++ oracle (top width Gamma_t, zero in t-channel
+propagators in the zero-width t-channel mode).
+
+Method, chosen for being checkable by eye rather than fast:
+  * every tree diagram is enumerated explicitly: the diagrams are the ways to
+    hang all legs but leg 0 from leg 0's vertex, each sub-tree being a QCD
+    vertex joining smaller sub-trees (one tree per Feynman diagram; the
+    four-gluon vertex contributes its three colour structures as three
+    terms);
+  * each diagram's Lorentz part is evaluated literally, in the Dirac
+    representation with explicit 4x4 gamma matrices, for every helicity;
+  * each diagram's colour factor is the explicit tensor over the colours of
+    all external legs, contracted from t^a (Gell-Mann matrices / 2) and
+    f^{abc} = -2i Tr(t^a [t^b, t^c]) with every internal index summed; the
+    colour sum is then sum_{d,e} conj(M_d) G_de M_e with the diagram-basis
+    Gram matrix G_de = sum over all external colours of conj(c_d) c_e;
+  * with two or more fermion lines, each diagram carries the sign of the
+    permutation that takes the external fermions, in leg order, to the order
+    (row end, column end) line by line (Fermi statistics);
+  * external momenta on the mass shell (energy from the three-momentum), as
+    in the C++ oracle;
+  * float64 or extended precision (numpy longdouble) throughout, colour
+    factors included.
+
+Legs in the order of the process string, legs 0 and 1 incoming; leg i has
+helicity +1 iff bit i of h is set.  IDEN = (initial spins) x (initial
+colours) x (n! per species of identical final particles).
+"""
+from __future__ import annotations
+
+import itertools
+from functools import lru_cache
+
+import numpy as np
+
+QUARKS = ("u", "d", "t")
+
+
+def _anti(name: str) -> str:
+    return name[:-1] if name.endswith("~") else name + "~"
+
+
+def parse(process: str):
+    """Legs (name, incoming) of "a b > c d ..."."""
+    ins, outs = process.split(">")
+    legs = [(x, True) for x in ins.split()] + [(x, False) for x in outs.split()]
+    for x, _ in legs:
+        if x != "g" and x.rstrip("~") not in QUARKS:
+            raise ValueError(f"unknown particle {x}")
+    return legs
+
+
+def iden(process: str) -> int:
+    legs = parse(process)
+    d = 1
+    for x, inc in legs:
+        if inc:
+            d *= 2 * (8 if x == "g" else 3)
+    finals = [x for x, inc in legs if not inc]
+    for x in set(finals):
+        for k in range(2, finals.count(x) + 1):
+            d *= k
+    return d
+
+
+# ------------------------------------------------------------------ colour
+@lru_cache(maxsize=None)
+def _su3(dtype_name: str):
+    dt = np.dtype(dtype_name)
+    cdt = np.result_type(dt, np.complex64)
+    one, half = dt.type(1), dt.type(0.5)
+    r3 = one / np.sqrt(dt.type(3))
+    t = np.zeros((8, 3, 3), dtype=cdt)
+    t[0][0, 1] = t[0][1, 0] = 1
+    t[1][0, 1], t[1][1, 0] = -1j, 1j
+    t[2][0, 0], t[2][1, 1] = 1, -1
+    t[3][0, 2] = t[3][2, 0] = 1
+    t[4][0, 2], t[4][2, 0] = -1j, 1j
+    t[5][1, 2] = t[5][2, 1] = 1
+    t[6][1, 2], t[6][2, 1] = -1j, 1j
+    t[7][0, 0] = t[7][1, 1] = r3
+    t[7][2, 2] = -2 * r3
+    t = t * half
+    comm = np.einsum("bjk,cki->bcji", t, t) - np.einsum("cjk,bki->bcji", t, t)
+    f = (-2j * np.einsum("aij,bcji->abc", t, comm)).real.astype(dt)
+    f[np.abs(f) < dt.type(1e-12)] = 0
+    return t, f
+
+
+# --------------------------------------------------------------- diagrams
+class Node:
+    """A sub-tree: the legs `legs` joined by vertices into one line entering
+    its parent vertex.  kind: 'g' (gluon current), 'col' or 'row' (a fermion
+    line whose column or row end is inside), 'amp' (the whole diagram).
+    op: how it is built from its children; lines: completed fermion lines
+    (row end, column end) inside; end: the open fermion end leg."""
+    __slots__ = ("kind", "flav", "legs", "op", "kids", "piece", "lines", "end")
+
+    def __init__(self, kind, flav, legs, op, kids, piece=None, lines=(), end=None):
+        self.kind, self.flav, self.legs, self.op, self.kids = kind, flav, legs, op, kids
+        self.piece, self.lines, self.end = piece, lines, end
+
+
+class Process:
+    """The diagrams of a process and their colour Gram matrix."""
+
+    def __init__(self, process: str):
+        self.process = process
+        self.legs = parse(process)
+        self.n = len(self.legs)
+        self.iden = iden(process)
+        # field of each leg in the all-outgoing convention
+        self.field = [x if not inc or x == "g" else _anti(x) for x, inc in self.legs]
+        self._memo = {}
+        self.diagrams = self._enumerate()
+        self._gram = {}
+
+    # leg as a line end: outgoing quarks and incoming antiquarks are row
+    # ends (ubar, vbar), outgoing antiquarks and incoming quarks column ends
+    def _leaf(self, i):
+        f = self.field[i]
+        if f == "g":
+            return Node("g", None, frozenset([i]), "ext", ())
+        if f.endswith("~"):
+            return Node("col", f[:-1], frozenset([i]), "ext", (), end=i)
+        return Node("row", f, frozenset([i]), "ext", (), end=i)
+
+    def _splits(self, S, k):
+        """Unordered partitions of the sorted tuple S into k non-empty blocks."""
+        S = tuple(sorted(S))
+        if k == 1:
+            yield (frozenset(S),)
+            return
+        first, rest = S[0], S[1:]
+        for r in range(len(rest) + 1):
+            for extra in itertools.combinations(rest, r):
+                A = frozenset((first,) + extra)
+                B = [x for x in rest if x not in extra]
+                if len(B) < k - 1:
+                    continue
+                for tail in self._splits(B, k - 1):
+                    yield (A,) + tail
+
+    def currents(self, S):
+        """Every sub-tree over the legs S (a frozenset)."""
+        if S in self._memo:
+            return self._memo[S]
+        out = []
+        if len(S) == 1:
+            out.append(self._leaf(next(iter(S))))
+        else:
+            for A, B in self._splits(S, 2):
+                for x, y in itertools.product(self.currents(A), self.currents(B)):
+                    out.extend(self._join2(x, y, S))
+            for A, B, C in self._splits(S, 3):
+                for x, y, z in itertools.product(self.currents(A), self.currents(B), self.currents(C)):
+                    if x.kind == y.kind == z.kind == "g":
+                        for piece in range(3):
+                            out.append(Node("g", None, S, "gggg", (x, y, z), piece=piece,
+                                            lines=x.lines + y.lines + z.lines))
+        self._memo[S] = out
+        return out
+
+    def _join2(self, x, y, S):
+        res = []
+        lines = x.lines + y.lines
+        for a, b in ((x, y), (y, x)):
+            if a.kind == "col" and b.kind == "g":
+                res.append(Node("col", a.flav, S, "col_g", (a, b), lines=lines, end=a.end))
+            if a.kind == "row" and b.kind == "g":
+                res.append(Node("row", a.flav, S, "row_g", (a, b), lines=lines, end=a.end))
+            if a.kind == "row" and b.kind == "col" and a.flav == b.flav:
+                res.append(Node("g", None, S, "row_col", (a, b), lines=lines + ((a.end, b.end),)))
+        if x.kind == "g" and y.kind == "g":
+            res.append(Node("g", None, S, "ggg", (x, y), lines=lines))
+        return res
+
+    def _enumerate(self):
+        root = self._leaf(0)
+        rest = frozenset(range(1, self.n))
+        out = []
+        for parts in itertools.chain(self._splits(rest, 2), self._splits(rest, 3)):
+            for kids in itertools.product(*[self.currents(P) for P in parts]):
+                lines = sum((k.lines for k in kids), ())
+                kinds = [k.kind for k in kids]
+                if len(kids) == 3:
+                    if root.kind == "g" and kinds == ["g", "g", "g"]:
+                        for piece in range(3):
+                            out.append(Node("amp", None, None, "root_gggg", kids, piece=piece, lines=lines))
+                    continue
+                x, y = kids
+                if root.kind == "g":
+                    if kinds == ["g", "g"]:
+                        out.append(Node("amp", None, None, "root_ggg", (x, y), lines=lines))
+                    for a, b in ((x, y), (y, x)):
+                        if a.kind == "row" and b.kind == "col" and a.flav == b.flav:
+                            out.append(Node("amp", None, None, "root_row_col", (a, b),
+                                            lines=lines + ((a.end, b.end),)))
+                else:
+                    for a, b in ((x, y), (y, x)):
+                        if b.kind != "g":
+                            continue
+                        if root.kind == "row" and a.kind == "col" and a.flav == root.flav:
+                            out.append(Node("amp", None, None, "root_rowend", (a, b),
+                                            lines=lines + ((0, a.end),)))
+                        if root.kind == "col" and a.kind == "row" and a.flav == root.flav:
+                            out.append(Node("amp", None, None, "root_colend", (a, b),
+                                            lines=lines + ((a.end, 0),)))
+        return out
+
+    # ------------------------------------------------------------ signs
+    def sign(self, d) -> int:
+        """Parity of the permutation taking the fermion legs in leg order to
+        (row end, column end) of each line in turn."""
+        seq = [i for line in sorted(d.lines) for i in line]
+        inv = sum(1 for a in range(len(seq)) for b in range(a + 1, len(seq)) if seq[a] > seq[b])
+        return -1 if inv % 2 else 1
+
+    # ----------------------------------------------------------- colour
+    def _dims(self):
+        return [8 if f == "g" else 3 for f in self.field]
+
+    def colour_tensor(self, d, dtype):
+        """Explicit colour factor of diagram d over the colours of legs
+        0..n-1 (numpy array of shape dims)."""
+        t, f = _su3(np.dtype(dtype).name)
+        letters = "abcdefghijklmnop"
+        leg_ax = {i: letters[i] for i in range(self.n)}
+
+        def ax(node):
+            return "".join(leg_ax[i] for i in sorted(node.legs))
+
+        def tens(node):
+            """array with axes (legs of node in order) + own index."""
+            if node.op == "ext":
+                k = self._dims()[next(iter(node.legs))]
+                return np.eye(k, dtype=t.dtype)
+            kids = [tens(k) for k in node.kids]
+            sub = [ax(k) for k in node.kids]
+            out = ax(node)
+            if node.op == "col_g":      # t^a_{i i'} C_{.. i'} G_{.. a}
+                return np.einsum(f"{sub[0]}Y,{sub[1]}A,AXY->{out}X", kids[0], kids[1], t)
+            if node.op == "row_g":      # R_{.. j'} t^a_{j' j} G_{.. a}
+                return np.einsum(f"{sub[0]}Y,{sub[1]}A,AYX->{out}X", kids[0], kids[1], t)
+            if node.op == "row_col":    # t^x_{j i} R_{.. j} C_{.. i}
+                return np.einsum(f"{sub[0]}Y,{sub[1]}Z,XYZ->{out}X", kids[0], kids[1], t)
+            if node.op == "ggg":        # f^{x a b} A_a B_b
+                return np.einsum(f"{sub[0]}Y,{sub[1]}Z,XYZ->{out}X", kids[0], kids[1], f)
+            if node.op == "gggg":       # f^{x y e} f^{e z w} for the piece's inputs
+                order = [(0, 1, 2), (1, 0, 2), (2, 0, 1)][node.piece]
+                y, z, w = [kids[k] for k in order]
+                sy, sz, sw = [sub[k] for k in order]
+                return np.einsum(f"{sy}Y,{sz}Z,{sw}W,XYE,EZW->{out}X", y, z, w, f, f)
+            raise ValueError(node.op)
+
+        kids = [tens(k) for k in d.kids]
+        sub = [ax(k) for k in d.kids]
+        r = leg_ax[0]
+        if d.op == "root_ggg":
+            val = np.einsum(f"{sub[0]}Y,{sub[1]}Z,{r}YZ->{r}{sub[0]}{sub[1]}", kids[0], kids[1], f)
+        elif d.op == "root_gggg":
+            order = [(0, 1, 2), (1, 0, 2), (2, 0, 1)][d.piece]
+            y, z, w = [kids[k] for k in order]
+            sy, sz, sw = [sub[k] for k in order]
+            val = np.einsum(f"{sy}Y,{sz}Z,{sw}W,{r}YE,EZW->{r}{''.join(sub)}", y, z, w, f, f)
+        elif d.op == "root_row_col":
+            val = np.einsum(f"{sub[0]}Y,{sub[1]}Z,{r}YZ->{r}{sub[0]}{sub[1]}", kids[0], kids[1], t)
+        elif d.op == "root_rowend":     # t^a_{r i} C_i G_a
+            val = np.einsum(f"{sub[0]}Y,{sub[1]}A,A{r}Y->{r}{sub[0]}{sub[1]}", kids[0], kids[1], t)
+        elif d.op == "root_colend":     # R_j t^a_{j r} G_a
+            val = np.einsum(f"{sub[0]}Y,{sub[1]}A,AY{r}->{r}{sub[0]}{sub[1]}", kids[0], kids[1], t)
+        else:
+            raise ValueError(d.op)
+        cur = r + "".join(sub)
+        return np.einsum(f"{cur}->{''.join(sorted(cur))}", val)
+
+    def gram(self, dtype=np.float64):
+        key = np.dtype(dtype).name
+        if key not in self._gram:
+            C = np.stack([self.colour_tensor(d, dtype).reshape(-1) for d in self.diagrams])
+            self._gram[key] = np.conj(C) @ C.T
+        return self._gram[key]
+
+
+@lru_cache(maxsize=None)
+def process(name: str) -> Process:
+    return Process(name)
+
+
+# ----------------------------------------------------------- Lorentz part
+class _Dirac:
+    def __init__(self, cdt):
+        i2, z2 = np.eye(2), np.zeros((2, 2))
+        sig = [np.array([[0, 1], [1, 0]]), np.array([[0, -1j], [1j, 0]]), np.array([[1, 0], [0, -1]])]
+        g0 = np.block([[i2, z2], [z2, -i2]])
+        self.g = np.array([g0] + [np.block([[z2, s], [-s, z2]]) for s in sig]).astype(cdt)
+        self.eta = np.array([1, -1, -1, -1]).astype(cdt)
+
+    def slash(self, v):
+        """gamma^mu v_mu for contravariant v of shape (n, 4)."""
+        return np.einsum("nm,mij->nij", v * self.eta, self.g)
+
+
+def _mdot(a, b):
+    return a[:, 0] * b[:, 0] - a[:, 1] * b[:, 1] - a[:, 2] * b[:, 2] - a[:, 3] * b[:, 3]
+
+
+def _chi(p, lam, cdt):
+    pt = np.sqrt(p[:, 1] ** 2 + p[:, 2] ** 2)
+    th = np.arctan2(pt, p[:, 3])
+    ph = np.where(pt > 0, np.arctan2(p[:, 2], p[:, 1]), 0 * pt)
+    c, s = np.cos(th / 2), np.sin(th / 2)
+    e = np.cos(ph) + 1j * np.sin(ph)
+    x = np.zeros((p.shape[0], 2), dtype=cdt)
+    if lam > 0:
+        x[:, 0], x[:, 1] = c, e * s
+    else:
+        x[:, 0], x[:, 1] = -np.conj(e) * s, c
+    return x
+
+
+def _u(p, m, lam, cdt):
+    x = _chi(p, lam, cdt)
+    a = np.sqrt(p[:, 0] + m)
+    b = lam * np.sqrt(p[:, 1] ** 2 + p[:, 2] ** 2 + p[:, 3] ** 2) / a
+    return np.concatenate([a[:, None] * x, b[:, None] * x], axis=1)
+
+
+def _v(p, m, lam, cdt):
+    x = _chi(p, -lam, cdt)
+    a = np.sqrt(p[:, 0] + m)
+    b = -lam * np.sqrt(p[:, 1] ** 2 + p[:, 2] ** 2 + p[:, 3] ** 2) / a
+    return np.concatenate([b[:, None] * x, a[:, None] * x], axis=1)
+
+
+def _bar(s):
+    r = np.conj(s)
+    r[:, 2:] = -r[:, 2:]
+    return r
+
+
+def _eps(k, lam, cdt):
+    pt = np.sqrt(k[:, 1] ** 2 + k[:, 2] ** 2)
+    th = np.arctan2(pt, k[:, 3])
+    ph = np.where(pt > 0, np.arctan2(k[:, 2], k[:, 1]), 0 * pt)
+    z = 0 * pt
+    e1 = np.stack([z, np.cos(th) * np.cos(ph), np.cos(th) * np.sin(ph), -np.sin(th)], axis=1)
+    e2 = np.stack([z, -np.sin(ph), np.cos(ph), z], axis=1)
+    return ((-lam * e1 - 1j * e2) / np.sqrt(k.dtype.type(2))).astype(cdt)
+
+
+def _params(params):
+    """(g_s, mt, wt, wt in t-channel) from a C++ oracle parameter block or a dict."""
+    get = (lambda k: getattr(params, k)) if not isinstance(params, dict) else params.__getitem__
+    return get("alpha_s"), get("mt"), get("wt"), get("tchan_zero_width")
+
+
+def me(process_name: str, mom, params, long_double: bool = False, per_helicity: bool = False,
+       gauge_leg: int = -1):
+    """|M|^2 of events mom [nevt][n][4] (float64); per_helicity: the
+    colour-summed |M_h|^2 of every helicity, [nevt][2^n] (no 1/IDEN).
+    gauge_leg >= 0 (a gluon): its polarisation vector is replaced by k/k^0
+    (the Ward identity makes the result vanish)."""
+    P = process(process_name)
+    dt = np.longdouble if long_double else np.float64
+    cdt = np.clongdouble if long_double else np.complex128
+    alpha_s, mt, wt, tzero = _params(params)
+    pi = np.arccos(dt(-1))
+    gs = np.sqrt(4 * pi * dt(alpha_s))
+    mt, wt = dt(mt), dt(wt)
+    D = _Dirac(cdt)
+    mom = np.asarray(mom, dtype=np.float64)
+    nevt = mom.shape[0]
+    p = mom.astype(dt)
+    mass = [mt if x.rstrip("~") == "t" else dt(0) for x, _ in P.legs]
+    for i in range(P.n):   # on the mass shell
+        e = np.sqrt(mass[i] ** 2 + p[:, i, 1] ** 2 + p[:, i, 2] ** 2 + p[:, i, 3] ** 2)
+        p[:, i, 0] = np.where(mom[:, i, 0] < 0, -e, e)
+    inc = [x for _, x in P.legs]
+    kin = [p[:, i] if inc[i] else -p[:, i] for i in range(P.n)]   # momentum into the diagram
+    G = P.gram(dt).astype(cdt)
+    signs = np.array([P.sign(d) for d in P.diagrams], dtype=dt)
+    one = np.eye(4, dtype=cdt)[None]
+    nhel = 1 << P.n
+    out_h = np.zeros((nevt, nhel), dtype=dt)
+
+    def ksum(S):
+        return sum(kin[i] for i in S)
+
+    def prop_f(S, flav, P_):
+        m = mt if flav == "t" else dt(0)
+        w = dt(0)
+        if flav == "t":
+            nin = sum(1 for i in S if inc[i])
+            w = dt(0) if (tzero and nin == 1) else wt
+        den = _mdot(P_, P_) - m * m + 1j * m * w
+        return 1j * (D.slash(P_) + m * one) / den[:, None, None]
+
+    def g_prop(S):
+        K = ksum(S)
+        return -1j / _mdot(K, K)
+
+    for h in range(nhel):
+        lam = [1 if (h >> i) & 1 else -1 for i in range(P.n)]
+        ext = {}
+        for i, (x, incoming) in enumerate(P.legs):
+            f = P.field[i]
+            if f == "g":
+                e = _eps(p[:, i], lam[i], cdt) if i != gauge_leg else (p[:, i] / p[:, i, :1]).astype(cdt)
+                ext[i] = e if incoming else np.conj(e)
+            else:
+                q = x.rstrip("~") != x   # physical particle is an antiquark
+                if f.endswith("~"):       # column end
+                    ext[i] = _v(p[:, i], mass[i], lam[i], cdt) if q else _u(p[:, i], mass[i], lam[i], cdt)
+                else:                     # row end
+                    ext[i] = _bar(_v(p[:, i], mass[i], lam[i], cdt)) if q else \
+                        _bar(_u(p[:, i], mass[i], lam[i], cdt))
+        memo = {}
+
+        def val(node):
+            key = id(node)
+            if key in memo:
+                return memo[key]
+            if node.op == "ext":
+                r = ext[next(iter(node.legs))]
+            elif node.op == "col_g":    # S_F(K) (i g gamma.G) psi
+                c, g = val(node.kids[0]), val(node.kids[1])
+                r = np.einsum("nij,nj->ni", prop_f(node.legs, node.flav, ksum(node.legs)),
+                              np.einsum("nij,nj->ni", 1j * gs * D.slash(g), c))
+            elif node.op == "row_g":    # psibar (i g gamma.G) S_F(-K)
+                rr, g = val(node.kids[0]), val(node.kids[1])
+                r = np.einsum("ni,nij->nj", np.einsum("ni,nij->nj", rr, 1j * gs * D.slash(g)),
+                              prop_f(node.legs, node.flav, -ksum(node.legs)))
+            elif node.op == "row_col":  # (-i g_{mu nu}/K^2) (i g psibar gamma^mu psi)
+                rr, c = val(node.kids[0]), val(node.kids[1])
+                J = np.stack([np.einsum("ni,ij,nj->n", rr, D.g[m], c) for m in range(4)], axis=1)
+                r = (g_prop(node.legs) * 1j * gs)[:, None] * J
+            elif node.op == "ggg":
+                A, B = val(node.kids[0]), val(node.kids[1])
+                pa, pb = ksum(node.kids[0].legs), ksum(node.kids[1].legs)
+                k = -(pa + pb)
+                W = A * _mdot(k - pa, B)[:, None] + _mdot(A, B)[:, None] * (pa - pb) + \
+                    B * _mdot(pb - k, A)[:, None]
+                r = (g_prop(node.legs) * gs)[:, None] * W
+            elif node.op == "gggg":
+                order = [(0, 1, 2), (1, 0, 2), (2, 0, 1)][node.piece]
+                Y, Z, Wv = [val(node.kids[k]) for k in order]
+                Pc = Z * _mdot(Y, Wv)[:, None] - Wv * _mdot(Y, Z)[:, None]
+                r = (g_prop(node.legs) * (-1j) * gs * gs)[:, None] * Pc
+            else:
+                raise ValueError(node.op)
+            memo[key] = r
+            return r
+
+        amps = []
+        X = ext[0]
+        for d in P.diagrams:
+            kids = [val(k) for k in d.kids]
+            if d.op == "root_ggg":
+                A, B = kids
+                pa, pb = ksum(d.kids[0].legs), ksum(d.kids[1].legs)
+                kx = kin[0]
+                a = gs * (_mdot(X, A) * _mdot(kx - pa, B) + _mdot(A, B) * _mdot(pa - pb, X) +
+                          _mdot(B, X) * _mdot(pb - kx, A))
+            elif d.op == "root_gggg":
+                order = [(0, 1, 2), (1, 0, 2), (2, 0, 1)][d.piece]
+                Y, Z, Wv = [kids[k] for k in order]
+                a = -1j * gs * gs * (_mdot(X, Z) * _mdot(Y, Wv) - _mdot(X, Wv) * _mdot(Y, Z))
+            elif d.op == "root_row_col":
+                rr, c = kids
+                a = np.einsum("ni,nij,nj->n", rr, 1j * gs * D.slash(X), c)
+            elif d.op == "root_rowend":
+                c, g = kids
+                a = np.einsum("ni,nij,nj->n", X, 1j * gs * D.slash(g), c)
+            elif d.op == "root_colend":
+                rr, g = kids
+                a = np.einsum("ni,nij,nj->n", rr, 1j * gs * D.slash(g), X)
+            else:
+                raise ValueError(d.op)
+            amps.append(a)
+        A = np.stack(amps, axis=1) * signs[None, :]
+        out_h[:, h] = np.einsum("nd,de,ne->n", np.conj(A), G, A).real
+    if per_helicity:
+        return out_h.astype(np.float64)
+    return (out_h.sum(axis=1) / dt(P.iden)).astype(np.float64)
