@@ -33,7 +33,8 @@ Method, chosen for being checkable by eye rather than fast:
     permutation that takes the external fermions, in leg order, to the order
     (row end, column end) line by line (Fermi statistics);
   * external momenta on the mass shell (energy from the three-momentum), as
-    in the C++ oracle;
+    in the C++ oracle; the momentum of an internal line is summed over the
+    side of the line with fewer external legs;
   * float64 or extended precision (numpy longdouble) throughout, colour
     factors included.
 
@@ -399,8 +400,16 @@ def me(process_name: str, mom, params, long_double: bool = False, per_helicity: 
     nhel = 1 << P.n
     out_h = np.zeros((nevt, nhel), dtype=dt)
 
+    # The momentum of the line that joins the legs S to the rest: double
+    # inputs balance only to rounding (~1e-13 GeV), and for an invariant far
+    # below E^2 that imbalance decides its last digits, so the value taken
+    # must not depend on how the diagram happens to be oriented.  Reading:
+    # the sum over the side of the line with fewer legs (S itself on a tie:
+    # every current excludes leg 0).
     def ksum(S):
-        return sum(kin[i] for i in S)
+        if len(S) <= P.n - len(S):
+            return sum(kin[i] for i in S)
+        return -sum(kin[i] for i in range(P.n) if i not in S)
 
     def prop_f(S, flav, P_):
         m = mt if flav == "t" else dt(0)

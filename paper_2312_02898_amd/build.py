@@ -24,7 +24,9 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libme_mi355x.so")
 
 PROCESSES = ["eemumu", "ggtt", "ggttg", "ggttgg", "ggttggg", "uutt", "uxutt",
-             "uuttg", "uxuttg", "ugttu", "guttu", "uxgttux", "guxttux"]
+             "uuttg", "uxuttg", "ugttu", "guttu", "uxgttux", "guxttux",
+             "uuttgg", "uxuttgg", "ugttug", "guttug", "uxgttuxg", "guxttuxg", "ggttuux",
+             "uuttuux", "uuttddx", "uuttuu", "udttud", "uxuxttuxux"]
 
 HIPCC = os.environ.get("HIPCC", "hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -21,6 +21,18 @@ PROCESS_NAMES = {
     "guttu": "g u > t t~ u",
     "uxgttux": "u~ g > t t~ u~",
     "guxttux": "g u~ > t t~ u~",
+    "uuttgg": "u u~ > t t~ g g",
+    "uxuttgg": "u~ u > t t~ g g",
+    "ugttug": "u g > t t~ u g",
+    "guttug": "g u > t t~ u g",
+    "uxgttuxg": "u~ g > t t~ u~ g",
+    "guxttuxg": "g u~ > t t~ u~ g",
+    "ggttuux": "g g > t t~ u u~",
+    "uuttuux": "u u~ > t t~ u u~",
+    "uuttddx": "u u~ > t t~ d d~",
+    "uuttuu": "u u > t t~ u u",
+    "udttud": "u d > t t~ u d",
+    "uxuxttuxux": "u~ u~ > t t~ u~ u~",
 }
 
 

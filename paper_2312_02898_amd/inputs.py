@@ -39,6 +39,11 @@ PROCESS_LEGS = {
     "u~ g > t t~ u~": (0.0, 0.0, 173.0, 173.0, 0.0),
     "g u~ > t t~ u~": (0.0, 0.0, 173.0, 173.0, 0.0),
 }
+# two-jet channels of p p > t t~: t t~ and two massless partons
+for _p in ("u u~ > t t~ g g", "u~ u > t t~ g g", "u g > t t~ u g", "g u > t t~ u g", "u~ g > t t~ u~ g",
+           "g u~ > t t~ u~ g", "g g > t t~ u u~", "u u~ > t t~ u u~", "u u~ > t t~ d d~", "u u > t t~ u u",
+           "u d > t t~ u d", "u~ u~ > t t~ u~ u~"):
+    PROCESS_LEGS[_p] = (0.0, 0.0, 173.0, 173.0, 0.0, 0.0)
 
 
 def rambo(nevt: int, sqrt_s: float, final_masses, seed: int, rng=None) -> np.ndarray:
@@ -156,6 +161,19 @@ CONFIGS = {
     "guttu": ("g u > t t~ u", 1500.0, 1 << 20, 11),
     "uxgttux": ("u~ g > t t~ u~", 1500.0, 1 << 20, 12),
     "guxttux": ("g u~ > t t~ u~", 1500.0, 1 << 20, 13),
+    # two-jet channels of p p > t t~ (same kinematics as g g > t t~ g g)
+    "uuttgg": ("u u~ > t t~ g g", 1500.0, 1 << 20, 14),
+    "uxuttgg": ("u~ u > t t~ g g", 1500.0, 1 << 20, 15),
+    "ugttug": ("u g > t t~ u g", 1500.0, 1 << 20, 16),
+    "guttug": ("g u > t t~ u g", 1500.0, 1 << 20, 17),
+    "uxgttuxg": ("u~ g > t t~ u~ g", 1500.0, 1 << 20, 18),
+    "guxttuxg": ("g u~ > t t~ u~ g", 1500.0, 1 << 20, 19),
+    "ggttuux": ("g g > t t~ u u~", 1500.0, 1 << 20, 20),
+    "uuttuux": ("u u~ > t t~ u u~", 1500.0, 1 << 20, 21),
+    "uuttddx": ("u u~ > t t~ d d~", 1500.0, 1 << 20, 22),
+    "uuttuu": ("u u > t t~ u u", 1500.0, 1 << 20, 23),
+    "udttud": ("u d > t t~ u d", 1500.0, 1 << 20, 24),
+    "uxuxttuxux": ("u~ u~ > t t~ u~ u~", 1500.0, 1 << 20, 25),
 }
 
 

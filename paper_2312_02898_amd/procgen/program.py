@@ -45,7 +45,7 @@ from . import colour
 FLOPS = {
     "ext_u": 40, "ext_v": 40, "ext_ubar": 40, "ext_vbar": 40, "ext_eps": 30,
     "ffv_fin": 154, "ffv_fout": 154, "ffv_v0": 144, "ffv_vm": 170,
-    "vvv_v": 158, "vvvv_acc": 132,
+    "vvv_v": 158, "vvvv_acc": 132, "vvvv_v": 124,
     "amp_ffv": 98, "amp_vvv": 168, "amp_vvvv_acc": 150,
     "ffv_half_row": 64, "ffv_half_col": 64, "amp_dot": 30,
     "ffv_v0_ew": 144, "ffv_vm_ew": 170, "amp_ffv_ew": 98, "amp_ffv_ew_acc": 100,
@@ -77,8 +77,8 @@ def _zero_saving(op, eps) -> int:
     if k == "amp_vvv":
         x, a, b = isv[:3]
         return wdot(x, a) + wdot(a, b) + wdot(b, x) + 6 * (x + a + b)
-    if k in ("vvvv_acc", "amp_vvvv_acc"):
-        j = 1 if k == "vvvv_acc" else 2
+    if k in ("vvvv_acc", "amp_vvvv_acc", "vvvv_v"):
+        j = {"vvvv_acc": 1, "amp_vvvv_acc": 2, "vvvv_v": 0}[k]
         b, c, d = isv[j:j + 3]
         f = wdot(b, d) + wdot(b, c) + (22 if c and d else (12 if c or d else 0))
         if k == "amp_vvvv_acc":
@@ -851,6 +851,8 @@ def all_programs(budget=None):
                                   for ng, n in ((2, "ggtt"), (3, "ggttg"), (4, "ggttgg"), (5, "ggttggg"))]
     progs += [qqtt_program(True), qqtt_program(False)]
     progs += [qqg_program(n) for n in QQG_CHANNELS]
+    from .general import TWO_JET, general_program
+    progs += [general_program(n, proc) for n, proc in TWO_JET.items()]
     for p in progs:
         if p.name in SPLIT:
             split_program(p, SPLIT[p.name], budget)
@@ -883,10 +885,12 @@ F32_LDS_JAMPS = set()
 # mixed forms whose vector-ALU kernel forms the propagator factors once per
 # event into LDS instead of once per helicity
 DEN_CACHE_F32 = {"eemumu", "ggtt", "ggttg", "ggttgg", "uutt", "uxutt", "uuttg", "uxuttg", "ugttu", "guttu",
-                 "uxgttux", "guxttux"}
+                 "uxgttux", "guxttux", "uuttgg", "uxuttgg", "ugttug", "guttug", "uxgttuxg", "guxttuxg", "ggttuux",
+                 "uuttuux", "uuttddx", "uuttuu", "udttud", "uxuxttuxux"}
 # the same for FP64 forms whose jamps stay in registers
 DEN_CACHE_F64 = {"eemumu", "ggtt", "ggttg", "uutt", "uxutt", "uuttg", "uxuttg", "ugttu", "guttu", "uxgttux",
-                 "guxttux"}
+                 "guxttux", "uuttgg", "uxuttgg", "ugttug", "guttug", "uxgttuxg", "guxttuxg", "ggttuux",
+                 "uuttuux", "uuttddx", "uuttuu", "udttud", "uxuxttuxux"}
 # processes whose default mixed form (ME_MIXED) sums colours on FP16 hi+lo
 # MFMA; the others use the vector ALU (chosen by measurement)
 MIXED_MFMA = set()

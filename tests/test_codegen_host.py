@@ -179,7 +179,10 @@ def emu_dir(tmp_path_factory):
 
 
 @pytest.mark.parametrize("form", ["f64", "f32"])
-@pytest.mark.parametrize("proc,nevt", [("uutt", 64), ("uxutt", 64), ("uuttg", 48), ("ugttu", 48), ("guxttux", 48), ("ggttg", 64), ("ggttgg", 24), ("ggttggg", 3)])
+@pytest.mark.parametrize("proc,nevt", [("uutt", 64), ("uxutt", 64), ("uuttg", 48), ("ugttu", 48), ("guxttux", 48), ("ggttg", 64), ("ggttgg", 24), ("ggttggg", 3),
+                                       ("uuttgg", 24), ("uxuttgg", 16), ("ugttug", 24), ("guttug", 16),
+                                       ("uxgttuxg", 16), ("guxttuxg", 16), ("ggttuux", 24), ("uuttuux", 32),
+                                       ("uuttddx", 32), ("uuttuu", 32), ("udttud", 32), ("uxuxttuxux", 32)])
 def test_generated_program_matches_oracle(oracle_lib, emu_dir, proc, nevt, form):
     """FP64 schedule: within 1e-12 of the oracle; FP32 schedule (FP32
     vertices, FP64 kinematics): median <= 1e-5, max <= 1e-3."""
