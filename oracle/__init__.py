@@ -96,6 +96,7 @@ def lib():
         L.oracle_me_gauge.argtypes = [i, P(Params), P(d), ctypes.c_int64, P(d)]
         L.oracle_uniforms.argtypes = [ctypes.c_int64, i, ctypes.c_uint64, P(d)]
         L.oracle_rambo.argtypes = [ctypes.c_int64, i, P(d), d, ctypes.c_uint64, P(d)]
+        L.oracle_sample.argtypes = [ctypes.c_int64, i, P(d), d, ctypes.c_uint64, P(d), P(d)]
         _lib = L
     return _lib
 
@@ -242,3 +243,14 @@ def rambo(nevt, masses, sqrt_s, seed):
     if lib().oracle_rambo(int(nevt), int(m.size), _dp(m), float(sqrt_s), int(seed), _dp(out)) != 0:
         raise ValueError("oracle_rambo failed")
     return out
+
+
+def sample(nevt, masses, sqrt_s, seed):
+    """Importance-sampled momenta [nevt][nfinal+2][4] and phase-space
+    weights [nevt] from the Philox stream."""
+    m = np.ascontiguousarray(masses, dtype=np.float64)
+    out = np.empty((nevt, m.size + 2, 4), dtype=np.float64)
+    w = np.empty(nevt, dtype=np.float64)
+    if lib().oracle_sample(int(nevt), int(m.size), _dp(m), float(sqrt_s), int(seed), _dp(out), _dp(w)) != 0:
+        raise ValueError("oracle_sample failed")
+    return out, w

@@ -1022,9 +1022,103 @@ void rambo_event(int64_t e, int n, const double* mass, double sqrt_s, uint64_t s
   std::memcpy(out + 8, p.data(), sizeof(double) * 4 * n);
 }
 
+// ----------------------------------------------- importance-sampled points
+// Sequential two-body splitting (the structure of madevent's phase-space
+// channels): the centre-of-mass system splits off the last final particle
+// and a remainder, the remainder the next-to-last, ..., and the last
+// remainder decays into final particles 1 and 2.  Per split k the uniforms
+// are Philox words (event, 0x10000 + 2k + half): u0 the remainder's mass,
+// u1 the polar angle, u2 the azimuth, all in the decaying system's rest
+// frame (reached by a pure boost) with the polar axis along z.
+//   remainder mass: M^2 = Mmin^2 + (1 - u0^2)(Mmax^2 - Mmin^2), favouring a
+//     soft splitting (M near its maximum); dM^2/du0 = 2 u0 (Mmax^2 - Mmin^2)
+//   polar angle: c = sqrt(1+eps) tanh(y), y uniform in [-Y, Y] with
+//     Y = atanh(1/sqrt(1+eps)), eps = 1/100, so that c covers [-1, 1] with a
+//     density ~ 1/(1 + eps - c^2) peaked along the beams;
+//     dc/du1 = 2Y (1 + eps - c^2)/sqrt(1+eps)
+//   azimuth: phi = 2 pi u2.
+// Weight (phase-space Jacobian for dPhi_n = (2pi)^4 delta^4 prod d^3p /
+// ((2pi)^3 2E)), from the factorisation dPhi_n = prod_k dPhi_2(k) prod
+// dM_k^2/(2pi) with dPhi_2 = |p*|/(16 pi^2 M) dcos dphi:
+//   W = prod_splits |p*|/(16 pi^2 M) (dc/du1)(2 pi) x prod_masses 2 u0 (Mmax^2 - Mmin^2)/(2 pi).
+void boost_to_lab(const double* P, double M, double* p) {
+  // p: four-momentum in the rest frame of P (mass M) -> lab
+  const double e = (P[0] * p[0] + P[1] * p[1] + P[2] * p[2] + P[3] * p[3]) / M;
+  const double f = (p[0] + e) / (P[0] + M);
+  p[0] = e;
+  for (int k = 1; k < 4; ++k) p[k] += f * P[k];
+}
+
+void sample_event(int64_t e, int n, const double* mass, double sqrt_s, uint64_t seed, double* out, double* w) {
+  const double pi = std::acos(-1.0), eps = 0.01;
+  const double se = std::sqrt(1 + eps), Y = std::atanh(1 / se);
+  const uint32_t k0 = uint32_t(seed), k1 = uint32_t(seed >> 32);
+  std::vector<double> p(4 * n);
+  double P[4] = {sqrt_s, 0, 0, 0}, M = sqrt_s, W = 1.0;
+  double mrest = 0;
+  for (int i = 0; i < n; ++i) mrest += mass[i];
+  // particles split off in the order n-1, n-2, ..., 2, then (0, 1) together
+  for (int k = 0; k < n - 1; ++k) {
+    double u[4];
+    for (int half = 0; half < 2; ++half) {
+      Ctr c{{uint32_t(e), uint32_t(uint64_t(e) >> 32), uint32_t(0x10000 + 2 * k + half), 0u}};
+      Ctr r = philox(c, k0, k1);
+      u[2 * half] = unit53(r.v[0], r.v[1]);
+      u[2 * half + 1] = unit53(r.v[2], r.v[3]);
+    }
+    const bool last = k == n - 2;
+    const int ja = last ? 1 : n - 1 - k;        // the particle split off (the t~ at the last split)
+    const double ma = mass[ja];
+    mrest -= ma;
+    double Mr;                                  // mass of the remainder
+    if (last) {
+      Mr = mass[0];
+    } else {
+      const double lo = mrest, hi = M - ma;
+      const double m2 = lo * lo + (1 - u[0] * u[0]) * (hi * hi - lo * lo);
+      Mr = std::sqrt(m2);
+      W *= 2 * u[0] * (hi * hi - lo * lo) / (2 * pi);
+    }
+    const double lam = std::sqrt(std::max(0.0, (M * M - (ma + Mr) * (ma + Mr)) * (M * M - (ma - Mr) * (ma - Mr))));
+    const double ps = lam / (2 * M);
+    const double y = (2 * u[1] - 1) * Y;
+    const double c = se * std::tanh(y);
+    const double st = std::sqrt(std::max(0.0, 1 - c * c)), phi = 2 * pi * u[2];
+    W *= ps / (16 * pi * pi * M) * (2 * Y * (1 + eps - c * c) / se) * (2 * pi);
+    double pa[4] = {std::sqrt(ma * ma + ps * ps), ps * st * std::cos(phi), ps * st * std::sin(phi), ps * c};
+    double pr[4] = {std::sqrt(Mr * Mr + ps * ps), -pa[1], -pa[2], -pa[3]};
+    boost_to_lab(P, M, pa);
+    boost_to_lab(P, M, pr);
+    for (int q = 0; q < 4; ++q) p[4 * ja + q] = pa[q];
+    if (last) {
+      for (int q = 0; q < 4; ++q) p[q] = pr[q];
+    } else {
+      for (int q = 0; q < 4; ++q) P[q] = pr[q];
+      M = Mr;
+    }
+  }
+  const double h = sqrt_s / 2;
+  const double beams[8] = {h, 0, 0, h, h, 0, 0, -h};
+  std::memcpy(out, beams, sizeof(beams));
+  std::memcpy(out + 8, p.data(), sizeof(double) * 4 * n);
+  *w = W;
+}
+
 }  // namespace
 
 extern "C" {
+
+int oracle_sample(int64_t nevt, int nfinal, const double* masses, double sqrt_s, uint64_t seed, double* out,
+                  double* weight) {
+  if (nevt < 0 || nfinal < 2 || nfinal > 5 || !masses || (nevt > 0 && (!out || !weight))) return -1;
+  double msum = 0;
+  for (int i = 0; i < nfinal; ++i) msum += masses[i];
+  if (!(msum < sqrt_s)) return -1;
+#pragma omp parallel for schedule(static)
+  for (int64_t e = 0; e < nevt; ++e)
+    sample_event(e, nfinal, masses, sqrt_s, seed, out + e * 4 * (nfinal + 2), weight + e);
+  return 0;
+}
 
 int oracle_uniforms(int64_t nevt, int nfinal, uint64_t seed, double* out) {
   if (nevt < 0 || nfinal < 1 || (nevt > 0 && !out)) return -1;

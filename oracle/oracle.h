@@ -102,6 +102,13 @@ int oracle_colour_matrix(int ngluons, double* out);
 int oracle_uniforms(int64_t nevt, int nfinal, uint64_t seed, double* out);
 int oracle_rambo(int64_t nevt, int nfinal, const double* masses, double sqrt_s, uint64_t seed, double* out);
 
+/* Importance-sampled phase-space points (sequential two-body splitting with
+ * beam-peaked polar angles and soft-favouring remainder masses; the mapping
+ * is spelled out in oracle.cpp) and their phase-space weights:
+ * out[nevt][nfinal+2][4], weight[nevt]. */
+int oracle_sample(int64_t nevt, int nfinal, const double* masses, double sqrt_s, uint64_t seed, double* out,
+                  double* weight);
+
 #ifdef __cplusplus
 }
 #endif
