@@ -1031,7 +1031,9 @@ void rambo_event(int64_t e, int n, const double* mass, double sqrt_s, uint64_t s
 // u1 the polar angle, u2 the azimuth, all in the decaying system's rest
 // frame (reached by a pure boost) with the polar axis along z.
 //   remainder mass: M^2 = Mmin^2 + (1 - u0^2)(Mmax^2 - Mmin^2), favouring a
-//     soft splitting (M near its maximum); dM^2/du0 = 2 u0 (Mmax^2 - Mmin^2)
+//     soft splitting (M near its maximum); dM^2/du0 = 2 u0 (Mmax^2 - Mmin^2);
+//     the distances to both ends of the range are carried exactly (no
+//     cancellation in the two-body momenta near a threshold)
 //   polar angle: c = sqrt(1+eps) tanh(y), y uniform in [-Y, Y] with
 //     Y = atanh(1/sqrt(1+eps)), eps = 1/100, so that c covers [-1, 1] with a
 //     density ~ 1/(1 + eps - c^2) peaked along the beams;
@@ -1057,6 +1059,7 @@ void sample_event(int64_t e, int n, const double* mass, double sqrt_s, uint64_t 
   double P[4] = {sqrt_s, 0, 0, 0}, M = sqrt_s, W = 1.0;
   double mrest = 0;
   for (int i = 0; i < n; ++i) mrest += mass[i];
+  double gap = sqrt_s - mrest;                  // M minus the sum of the masses it still holds
   // particles split off in the order n-1, n-2, ..., 2, then (0, 1) together
   for (int k = 0; k < n - 1; ++k) {
     double u[4];
@@ -1070,16 +1073,21 @@ void sample_event(int64_t e, int n, const double* mass, double sqrt_s, uint64_t 
     const int ja = last ? 1 : n - 1 - k;        // the particle split off (the t~ at the last split)
     const double ma = mass[ja];
     mrest -= ma;
-    double Mr;                                  // mass of the remainder
+    double Mr, thr;                             // remainder mass; M - ma - Mr
     if (last) {
       Mr = mass[0];
+      thr = gap;
     } else {
-      const double lo = mrest, hi = M - ma;
-      const double m2 = lo * lo + (1 - u[0] * u[0]) * (hi * hi - lo * lo);
-      Mr = std::sqrt(m2);
-      W *= 2 * u[0] * (hi * hi - lo * lo) / (2 * pi);
+      // hi^2 - lo^2 = gap (hi + lo) and hi - Mr = u0^2 (hi^2 - lo^2) / (hi + Mr):
+      // no cancellation near either end of the range
+      const double lo = mrest, hi = M - ma, d2 = gap * (hi + lo);
+      const double x = 1 - u[0] * u[0];
+      Mr = std::sqrt(lo * lo + x * d2);
+      thr = u[0] * u[0] * d2 / (hi + Mr);
+      gap = x * d2 / (Mr + lo);
+      W *= 2 * u[0] * d2 / (2 * pi);
     }
-    const double lam = std::sqrt(std::max(0.0, (M * M - (ma + Mr) * (ma + Mr)) * (M * M - (ma - Mr) * (ma - Mr))));
+    const double lam = std::sqrt(std::max(0.0, thr * (M + ma + Mr) * (M - ma + Mr) * (M + ma - Mr)));
     const double ps = lam / (2 * M);
     const double y = (2 * u[1] - 1) * Y;
     const double c = se * std::tanh(y);
