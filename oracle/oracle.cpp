@@ -1033,11 +1033,12 @@ void rambo_event(int64_t e, int n, const double* mass, double sqrt_s, uint64_t s
 //   remainder mass: M^2 = Mmin^2 + (1 - u0^2)(Mmax^2 - Mmin^2), favouring a
 //     soft splitting (M near its maximum); dM^2/du0 = 2 u0 (Mmax^2 - Mmin^2);
 //     the distances to both ends of the range are carried exactly (no
-//     cancellation in the two-body momenta near a threshold)
+//     cancellation in the two-body momenta near a threshold, 1 - u0^2 taken
+//     as (1 - u0)(1 + u0))
 //   polar angle: c = sqrt(1+eps) tanh(y), y uniform in [-Y, Y] with
 //     Y = atanh(1/sqrt(1+eps)), eps = 1/100, so that c covers [-1, 1] with a
 //     density ~ 1/(1 + eps - c^2) peaked along the beams;
-//     dc/du1 = 2Y (1 + eps - c^2)/sqrt(1+eps)
+//     dc/du1 = 2Y (1 + eps - c^2)/sqrt(1+eps) = 2Y sqrt(1+eps)/cosh^2(y)
 //   azimuth: phi = 2 pi u2.
 // Weight (phase-space Jacobian for dPhi_n = (2pi)^4 delta^4 prod d^3p /
 // ((2pi)^3 2E)), from the factorisation dPhi_n = prod_k dPhi_2(k) prod
@@ -1081,7 +1082,7 @@ void sample_event(int64_t e, int n, const double* mass, double sqrt_s, uint64_t 
       // hi^2 - lo^2 = gap (hi + lo) and hi - Mr = u0^2 (hi^2 - lo^2) / (hi + Mr):
       // no cancellation near either end of the range
       const double lo = mrest, hi = M - ma, d2 = gap * (hi + lo);
-      const double x = 1 - u[0] * u[0];
+      const double x = (1 - u[0]) * (1 + u[0]);
       Mr = std::sqrt(lo * lo + x * d2);
       thr = u[0] * u[0] * d2 / (hi + Mr);
       gap = x * d2 / (Mr + lo);
@@ -1090,9 +1091,10 @@ void sample_event(int64_t e, int n, const double* mass, double sqrt_s, uint64_t 
     const double lam = std::sqrt(std::max(0.0, thr * (M + ma + Mr) * (M - ma + Mr) * (M + ma - Mr)));
     const double ps = lam / (2 * M);
     const double y = (2 * u[1] - 1) * Y;
-    const double c = se * std::tanh(y);
+    const double c = se * std::tanh(y), ch = std::cosh(y);
     const double st = std::sqrt(std::max(0.0, 1 - c * c)), phi = 2 * pi * u[2];
-    W *= ps / (16 * pi * pi * M) * (2 * Y * (1 + eps - c * c) / se) * (2 * pi);
+    // dc/du1 = 2Y (1 + eps - c^2)/sqrt(1+eps) = 2Y sqrt(1+eps)/cosh^2(y)
+    W *= ps / (16 * pi * pi * M) * (2 * Y * se / (ch * ch)) * (2 * pi);
     double pa[4] = {std::sqrt(ma * ma + ps * ps), ps * st * std::cos(phi), ps * st * std::sin(phi), ps * c};
     double pr[4] = {std::sqrt(Mr * Mr + ps * ps), -pa[1], -pa[2], -pa[3]};
     boost_to_lab(P, M, pa);
