@@ -254,6 +254,23 @@ me_status me_max_weight(const double* d_me, const double* d_factor, int64_t nevt
 me_status me_rambo(int64_t nevt, int32_t nfinal, const double* masses, double sqrt_s, uint64_t seed,
                    double* d_momenta, void* hip_stream);
 
+/* Device-side importance-sampled phase space (the structure of madevent's
+ * mappings, which the paper's Sec. 3 profiles as the remaining host hotspot
+ * once the matrix element runs on the GPU): sequential two-body splitting of
+ * the centre-of-mass system (final particle nfinal-1 first, the last
+ * remainder into particles 0 and 1), remainder masses favouring soft
+ * splittings and polar angles peaked along the beams, Philox4x32-10
+ * uniforms with key = seed and counter = (event, 0x10000 + 2 split + half).
+ * Writes d_momenta [nevt][nfinal+2][4] (device; beams (sqrt_s/2)(1,0,0,+-1),
+ * then the final particles with masses[0..nfinal) (host array, GeV)) and
+ * d_weight [nevt] (device): each point's phase-space weight for
+ * dPhi_n = (2pi)^4 delta^4 prod d^3p / ((2pi)^3 2E), so that the mean of
+ * weight x f estimates the phase-space integral of f (feed weight / (2 s)
+ * times PDFs to me_max_weight as its factor).  Asynchronous; nothing is
+ * allocated.  ME_EINVAL for bad sizes, null pointers or sum(masses) >= sqrt_s. */
+me_status me_sample(int64_t nevt, int32_t nfinal, const double* masses, double sqrt_s, uint64_t seed,
+                    double* d_momenta, double* d_weight, void* hip_stream);
+
 /* ------------------------------------------------------------ serving --
  * A persistent request loop for uneven |M|^2 batches of several processes,
  * as integration channels emit them (continuous batching).  A request's

@@ -80,7 +80,7 @@ EXPORTS = [
     "me_good_helicities", "me_info", "me_destroy", "me_last_error",
     "me_server_create", "me_server_submit", "me_server_poll", "me_server_wait", "me_server_stats",
     "me_server_destroy", "me_max_weight", "me_rambo", "me_compute_channels", "me_server_times",
-    "me_workspace_bytes", "me_compute_channels_noalloc",
+    "me_workspace_bytes", "me_compute_channels_noalloc", "me_sample",
 ]
 
 # fixed device workspace of me_compute_channels_noalloc (ME_NOALLOC_SCRATCH_BYTES)
@@ -112,6 +112,7 @@ def lib():
                 getattr(L, name).restype = i32
         L.me_max_weight.argtypes = [vp, vp, i64, vp, vp, vp]
         L.me_rambo.argtypes = [i64, i32, P(d), d, ctypes.c_uint64, vp, vp]
+        L.me_sample.argtypes = [i64, i32, P(d), d, ctypes.c_uint64, vp, vp, vp]
         L.me_compute_channels.argtypes = [P(vp), i32, vp, vp, vp, i64, vp, vp]
         L.me_compute_channels_noalloc.argtypes = [P(vp), i32, vp, vp, vp, i64, vp, vp]
         L.me_workspace_bytes.argtypes = [vp, i64, P(i64)]
@@ -189,6 +190,14 @@ def me_rambo(nevt: int, masses, sqrt_s: float, seed: int, d_momenta: int, stream
     m = (ctypes.c_double * len(masses))(*[float(x) for x in masses])
     _check(lib().me_rambo(int(nevt), len(masses), m, float(sqrt_s), int(seed), d_momenta or None, stream or None),
            "me_rambo")
+
+
+def me_sample(nevt: int, masses, sqrt_s: float, seed: int, d_momenta: int, d_weight: int, stream: int = 0) -> None:
+    """Device importance-sampled phase space: momenta into d_momenta
+    [nevt][len(masses)+2][4] and phase-space weights into d_weight [nevt]."""
+    m = (ctypes.c_double * len(masses))(*[float(x) for x in masses])
+    _check(lib().me_sample(int(nevt), len(masses), m, float(sqrt_s), int(seed), d_momenta or None,
+                           d_weight or None, stream or None), "me_sample")
 
 
 def me_compute_channels(handles, d_momenta: int, d_channel: int, d_alphas: int, nevt: int, d_out: int,

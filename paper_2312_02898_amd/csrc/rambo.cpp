@@ -134,7 +134,136 @@ __global__ __launch_bounds__(256) void rambo_kernel(int64_t nevt, RamboArgs a, d
     for (int k = 0; k < 4; ++k) o[8 + 4 * i + k] = p[i][k];
 }
 
+// ----------------------------------------------- importance-sampled points
+// A non-flat generator with the channel structure of madevent's phase-space
+// mappings: sequential two-body splitting.  The centre-of-mass system emits
+// final particle N-1, its remainder particle N-2, ..., and the last remainder
+// decays into particles 0 and 1.  Per split k, Philox words (event,
+// 0x10000 + 2k + half) give u0 (remainder mass), u1 (polar angle), u2
+// (azimuth), angles taken in the decaying system's rest frame (pure boost)
+// about the z axis:
+//   M^2 = Mmin^2 + (1 - u0^2)(Mmax^2 - Mmin^2)         (soft splittings favoured;
+//                                                       both ends of the range carried exactly)
+//   c = sqrt(1+eps) tanh(y), y = (2 u1 - 1) Y, Y = atanh(1/sqrt(1+eps)), eps = 1/100
+//                                                       (peaked along the beams)
+//   phi = 2 pi u2.
+// Weight = phase-space Jacobian for dPhi_n = (2pi)^4 delta^4 prod d^3p/((2pi)^3 2E):
+//   prod_splits |p*|/(16 pi^2 M) * 2Y (1+eps-c^2)/sqrt(1+eps) * 2 pi
+//     (the angular factor taken as 2Y sqrt(1+eps)/cosh^2(y), free of cancellation)
+//   * prod_remainder-masses 2 u0 (Mmax^2 - Mmin^2)/(2 pi).
+struct SampleArgs {
+  double sqrt_s;
+  double mass[kMaxFinal];
+  uint32_t k0, k1;
+};
+
+// rest-frame four-momentum q of a system P of mass M, boosted to the lab
+__device__ __forceinline__ void to_lab(const double (&P)[4], double M, double (&q)[4]) {
+  const double e = (P[0] * q[0] + P[1] * q[1] + P[2] * q[2] + P[3] * q[3]) / M;
+  const double f = (q[0] + e) / (P[0] + M);
+  q[0] = e;
+  q[1] += f * P[1];
+  q[2] += f * P[2];
+  q[3] += f * P[3];
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void sample_kernel(int64_t nevt, SampleArgs a, double* __restrict__ out,
+                                                     double* __restrict__ weight) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= nevt) return;
+  const double pi = 3.14159265358979323846, eps = 0.01;
+  const double se = sqrt(1.0 + eps), Y = atanh(1.0 / se);
+  double p[N][4];
+  double P[4] = {a.sqrt_s, 0.0, 0.0, 0.0};
+  double M = a.sqrt_s, W = 1.0, mrest = 0.0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) mrest += a.mass[i];
+  double gap = a.sqrt_s - mrest;                  // M minus the masses it still holds
+#pragma unroll
+  for (int k = 0; k < N - 1; ++k) {
+    const U4 r0 = philox4x32_10(U4{uint32_t(e), uint32_t(uint64_t(e) >> 32), uint32_t(0x10000 + 2 * k), 0u},
+                                a.k0, a.k1);
+    const U4 r1 = philox4x32_10(U4{uint32_t(e), uint32_t(uint64_t(e) >> 32), uint32_t(0x10000 + 2 * k + 1), 0u},
+                                a.k0, a.k1);
+    const double u0 = u53(r0.x, r0.y), u1 = u53(r0.z, r0.w), u2 = u53(r1.x, r1.y);
+    const bool last = k == N - 2;
+    const int ja = last ? 1 : N - 1 - k;          // particle split off here
+    const double ma = a.mass[ja];
+    mrest -= ma;
+    double Mr, thr;                               // remainder mass, M - ma - Mr
+    if (last) {
+      Mr = a.mass[0];
+      thr = gap;
+    } else {
+      // the distances to both ends of the mass range without cancellation
+      const double lo = mrest, hi = M - ma, d2 = gap * (hi + lo), x = (1.0 - u0) * (1.0 + u0);
+      Mr = sqrt(lo * lo + x * d2);
+      thr = u0 * u0 * d2 / (hi + Mr);
+      gap = x * d2 / (Mr + lo);
+      W *= 2.0 * u0 * d2 / (2.0 * pi);
+    }
+    const double ps = sqrt(fmax(0.0, thr * (M + ma + Mr) * (M - ma + Mr) * (M + ma - Mr))) / (2.0 * M);
+    const double y = (2.0 * u1 - 1.0) * Y, c = se * tanh(y), ch = cosh(y);
+    const double st = sqrt(fmax(0.0, 1.0 - c * c)), phi = 2.0 * pi * u2;
+    W *= ps / (16.0 * pi * pi * M) * (2.0 * Y * se / (ch * ch)) * (2.0 * pi);
+    double qa[4] = {sqrt(ma * ma + ps * ps), ps * st * cos(phi), ps * st * sin(phi), ps * c};
+    double qr[4] = {sqrt(Mr * Mr + ps * ps), -qa[1], -qa[2], -qa[3]};
+    to_lab(P, M, qa);
+    to_lab(P, M, qr);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) p[ja][q] = qa[q];
+    if (last) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) p[0][q] = qr[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) P[q] = qr[q];
+      M = Mr;
+    }
+  }
+  double* o = out + e * (4 * (N + 2));
+  const double h = 0.5 * a.sqrt_s;
+  o[0] = h; o[1] = 0.0; o[2] = 0.0; o[3] = h;
+  o[4] = h; o[5] = 0.0; o[6] = 0.0; o[7] = -h;
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o[8 + 4 * i + k] = p[i][k];
+  weight[e] = W;
+}
+
 }  // namespace
+
+extern "C" me_status me_sample(int64_t nevt, int32_t nfinal, const double* masses, double sqrt_s, uint64_t seed,
+                               double* d_momenta, double* d_weight, void* hip_stream) {
+  if (nevt < 0 || nfinal < 2 || nfinal > kMaxFinal || !masses || !(sqrt_s > 0) ||
+      (nevt > 0 && (!d_momenta || !d_weight)))
+    return ME_EINVAL;
+  SampleArgs a;
+  a.sqrt_s = sqrt_s;
+  double msum = 0.0;
+  for (int i = 0; i < kMaxFinal; ++i) a.mass[i] = i < nfinal ? masses[i] : 0.0;
+  for (int i = 0; i < nfinal; ++i) {
+    if (!(masses[i] >= 0)) return ME_EINVAL;
+    msum += masses[i];
+  }
+  if (!(msum < sqrt_s)) return ME_EINVAL;
+  a.k0 = uint32_t(seed);
+  a.k1 = uint32_t(seed >> 32);
+  if (nevt == 0) return ME_OK;
+  const int64_t blocks = (nevt + 255) / 256;
+  if (blocks > 0x7fffffffLL) return ME_EINVAL;
+  const dim3 grid{unsigned(blocks)}, block{256};
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  switch (nfinal) {
+    case 2: hipLaunchKernelGGL(sample_kernel<2>, grid, block, 0, s, nevt, a, d_momenta, d_weight); break;
+    case 3: hipLaunchKernelGGL(sample_kernel<3>, grid, block, 0, s, nevt, a, d_momenta, d_weight); break;
+    case 4: hipLaunchKernelGGL(sample_kernel<4>, grid, block, 0, s, nevt, a, d_momenta, d_weight); break;
+    default: hipLaunchKernelGGL(sample_kernel<5>, grid, block, 0, s, nevt, a, d_momenta, d_weight); break;
+  }
+  return hipGetLastError() == hipSuccess ? ME_OK : ME_EHIP;
+}
 
 extern "C" me_status me_rambo(int64_t nevt, int32_t nfinal, const double* masses, double sqrt_s, uint64_t seed,
                               double* d_momenta, void* hip_stream) {
