@@ -76,6 +76,11 @@ def measured_traffic(variant):
     return (m["fetch_kib"] * PMC_FETCH_SCALE + m["write_kib"] * PMC_WRITE_SCALE) * 1024.0
 
 
+def log(msg):
+    """Progress of the run on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def time_kernel(me, m, out, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -169,7 +174,9 @@ def main():
     info = me_mfma.info
     flops_evt = info["flops_per_event"]
 
+    log("g g > t t~ g g: FP64")
     wall64, k64 = time_kernel(me64, m, out64, args.steps, args.warmup)
+    log("g g > t t~ g g: mixed forms")
     out_v = torch.empty(args.nevt, dtype=torch.float64, device=dev)
     wall_m, k_m = time_kernel(me_mfma, m, out32, args.steps, args.warmup)
     wall_v, k_v = time_kernel(me_valu, m, out_v, args.steps, args.warmup)
@@ -212,6 +219,8 @@ def main():
                    "colour_sum": best,
                    "good_helicities": info["nhel_good"], "diagrams": info["ndiagrams"],
                    "colour_flows": info["ncolor"]},
+        "fp64_value": fp64_value,
+        "fp64_ms_per_step": wall64 / K * 1e3,
         "fp64": {"value": fp64_value, "unit": "ME/s", "ms_per_step": wall64 / K * 1e3, "dtype": "f64"},
         "mixed_variants": variants,
         "mixed_vs_fp64_speedup": value / fp64_value,
@@ -232,6 +241,7 @@ def main():
     # kernels write jamps to an HBM workspace, MFMA colour-sum kernel; one
     # step per form over 2^20 events of its own configuration (seed 5)
     if args.ggttggg_nevt > 0:
+        log("g g > t t~ g g g")
         n5 = args.ggttggg_nevt
         m5 = torch.from_numpy(config_events("ggttggg", n5)).to(dev)
         o5 = torch.empty(n5, dtype=torch.float64, device=dev)
@@ -300,7 +310,26 @@ def main():
             row1[prec] = {"value": nc / dt, "unit": "ME/s", "ms": dt * 1e3}
             mix.close()
         rec["pp_ttbar_1jet_channels"] = row1
-        del mc, chn, als, oc, m1, ch1
+        # p p > t t~ + 2 jets: g g > t t~ g g and the twelve quark channels
+        twojet = ["ggttgg", "uuttgg", "uxuttgg", "ugttug", "guttug", "uxgttuxg", "guxttuxg", "ggttuux",
+                  "uuttuux", "uuttddx", "uuttuu", "udttud", "uxuxttuxux"]
+        m2 = torch.from_numpy(config_events("ggttgg", nc)).to(dev)
+        ch2 = torch.from_numpy(rng.integers(0, len(twojet), size=nc).astype(np.int32)).to(dev)
+        row2 = {"nevt": nc, "channels": [PROCESS_NAMES[x] for x in twojet]}
+        for prec in ("fp64", "mixed"):
+            mix = ChannelMix(twojet, prec)
+            mix(m2, ch2, als, oc)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                mix(m2, ch2, als, oc)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / 3
+            row2[prec] = {"value": nc / dt, "unit": "ME/s", "ms": dt * 1e3}
+            mix.close()
+        rec["pp_ttbar_2jet_channels"] = row2
+        log("channel mixes done")
+        del mc, chn, als, oc, m1, ch1, m2, ch2
 
     # HBM-bound neighbours of the path: device phase-space generation and the
     # batch-unweighting reduction, timed with events on the current stream
@@ -326,6 +355,26 @@ def main():
     t_maxw = t_events(lambda: B.me_max_weight(out32.data_ptr(), fac.data_ptr(), n, w.data_ptr(), mx.data_ptr(),
                                               stream))
     HBM = 8e12
+    # importance-sampled points with their phase-space weights (192 B of
+    # momenta and 8 B of weight written per event), and the device pipeline
+    # sample -> |M|^2 -> event weights and their maximum (the flux factor
+    # 1/(2s), a constant, left out), for the headline mixed form and FP64
+    w_ps = torch.empty(n, dtype=torch.float64, device=dev)
+    t_samp = t_events(lambda: B.me_sample(n, masses, 1500.0, 4, d_gen.data_ptr(), w_ps.data_ptr(), stream))
+    rec["device_sample"] = {"events_per_s": n / t_samp, "ms": t_samp * 1e3,
+                            "roofline": {"bound": "hbm", "achieved": n * 200 / t_samp / 1e9, "peak": HBM / 1e9,
+                                         "unit": "GB/s", "frac": n * 200 / t_samp / HBM, "bytes_per_event": 200}}
+    pipe = {"nevt": n, "process": "g g > t t~ g g", "sampler": "sequential two-body, beam-peaked angles"}
+    o_pipe = torch.empty(n, dtype=torch.float64, device=dev)
+    for label, mep in (("mixed", me32), ("fp64", me64)):
+        def step():
+            B.me_sample(n, masses, 1500.0, 4, d_gen.data_ptr(), w_ps.data_ptr(), stream)
+            mep(d_gen, o_pipe)
+            B.me_max_weight(o_pipe.data_ptr(), w_ps.data_ptr(), n, w.data_ptr(), mx.data_ptr(), stream)
+        tp = t_events(step, reps=3)
+        pipe[label] = {"events_per_s": n / tp, "ms_per_step": tp * 1e3}
+    pipe["sample_share_of_mixed_step"] = t_samp / (pipe["mixed"]["ms_per_step"] * 1e-3)
+    rec["sample_me_weight_pipeline"] = pipe
     rec["device_rambo"] = {"events_per_s": n / t_rambo, "ms": t_rambo * 1e3,
                            "roofline": {"bound": "hbm", "achieved": n * 6 * 32 / t_rambo / 1e9, "peak": HBM / 1e9,
                                         "unit": "GB/s", "frac": n * 6 * 32 / t_rambo / HBM,
@@ -334,7 +383,9 @@ def main():
                          "roofline": {"bound": "hbm", "achieved": n * 24 / t_maxw / 1e9, "peak": HBM / 1e9,
                                       "unit": "GB/s", "frac": n * 24 / t_maxw / HBM, "bytes_per_event": 24}}
 
+    log("sampler, pipeline, RAMBO, unweighting done")
     if not args.no_cpu:
+        log("CPU baseline (oracle)")
         cb, ref, ncpu = cpu_baseline(mom_np)
         rec["cpu_baseline"] = cb
         e64 = np.abs(r64[:ncpu] / ref - 1.0)
@@ -364,9 +415,12 @@ def main():
         import oracle
         subsets = {"eemumu": 16384, "ggtt": 1 << 16, "ggttg": 1 << 13, "ggttgg": 1 << 11, "ggttggg": 192,
                    "uutt": 1 << 16, "uxutt": 1 << 16, "uuttg": 1 << 13, "uxuttg": 1 << 13, "ugttu": 1 << 13,
-                   "guttu": 1 << 13, "uxgttux": 1 << 13, "guxttux": 1 << 13}
+                   "guttu": 1 << 13, "uxgttux": 1 << 13, "guxttux": 1 << 13,
+                   "uuttgg": 1 << 11, "ugttug": 1 << 11, "ggttuux": 1 << 11, "uuttuux": 1 << 11,
+                   "uuttuu": 1 << 11}
         errs = {}
         for name, ns in subsets.items():
+            log(f"errors against the oracle: {name}")
             mom_s = config_events(name, ns)
             ref = oracle.me(PROCESS_NAMES[name], mom_s)
             ms = torch.from_numpy(mom_s).to(dev)
@@ -448,6 +502,7 @@ def main():
                     "peak_bytes_in_use": st["peak_bytes_in_use"], "admissions_past_waiting_head": st["bypassed"],
                     "per_process": per}
 
+        log("serving")
         runs = [serve(0.7, 4 << 30), serve(0.5, 4 << 30), serve(0.9, 4 << 30), serve(0.7, 256 << 20)]
         head = runs[0]
         rec["serving"] = {"requests": head["requests"], "p50_latency_ms": head["p50_latency_ms"],
