@@ -358,7 +358,9 @@ def main():
     # importance-sampled points with their phase-space weights (192 B of
     # momenta and 8 B of weight written per event), and the device pipeline
     # sample -> |M|^2 -> event weights and their maximum (the flux factor
-    # 1/(2s), a constant, left out), for the headline mixed form and FP64
+    # 1/(2s), a constant, left out), for the headline mixed form and FP64,
+    # with the weights in a kernel of their own and fused into the |M|^2
+    # kernel's epilogue
     w_ps = torch.empty(n, dtype=torch.float64, device=dev)
     t_samp = t_events(lambda: B.me_sample(n, masses, 1500.0, 4, d_gen.data_ptr(), w_ps.data_ptr(), stream))
     rec["device_sample"] = {"events_per_s": n / t_samp, "ms": t_samp * 1e3,
@@ -371,8 +373,14 @@ def main():
             B.me_sample(n, masses, 1500.0, 4, d_gen.data_ptr(), w_ps.data_ptr(), stream)
             mep(d_gen, o_pipe)
             B.me_max_weight(o_pipe.data_ptr(), w_ps.data_ptr(), n, w.data_ptr(), mx.data_ptr(), stream)
+        def step_fused():
+            B.me_sample(n, masses, 1500.0, 4, d_gen.data_ptr(), w_ps.data_ptr(), stream)
+            B.me_compute_weighted(mep.handle, d_gen.data_ptr(), n, w_ps.data_ptr(), o_pipe.data_ptr(), w.data_ptr(),
+                                  mx.data_ptr(), stream)
         tp = t_events(step, reps=3)
-        pipe[label] = {"events_per_s": n / tp, "ms_per_step": tp * 1e3}
+        tf = t_events(step_fused, reps=3)
+        pipe[label] = {"events_per_s": n / tp, "ms_per_step": tp * 1e3,
+                       "fused_weights": {"events_per_s": n / tf, "ms_per_step": tf * 1e3}}
     pipe["sample_share_of_mixed_step"] = t_samp / (pipe["mixed"]["ms_per_step"] * 1e-3)
     rec["sample_me_weight_pipeline"] = pipe
     rec["device_rambo"] = {"events_per_s": n / t_rambo, "ms": t_rambo * 1e3,

@@ -158,6 +158,21 @@ me_status me_helicity_filter(me_handle h);
 me_status me_compute(me_handle h, const double* d_momenta, int64_t nevt, double* d_me,
                      void* hip_stream);
 
+/* me_compute with the unweighting step of the paper's Sec. 3 (Table 2: the
+ * event weights and their batch maximum formed on the device) fused into the
+ * kernel that produces |M|^2: besides d_me [nevt] it stores, when d_w is not
+ * NULL, d_w[i] = max(d_me[i] * d_factor[i], 0) (NaN clamped to 0 as well),
+ * and *d_max receives the maximum weight (0 for nevt == 0).  Bit for bit the
+ * result of me_compute followed by me_max_weight(d_me, d_factor, nevt, d_w,
+ * d_max).  All pointers are device pointers owned by the caller; d_factor
+ * [nevt] holds each event's Jacobian x PDF factor.  Asynchronous on
+ * hip_stream; *d_max is cleared on the stream by a kernel (no memset), so
+ * the call may be captured in a graph except for "g g > t t~ g g g", whose
+ * workspace is allocated as in me_compute.  ME_EINVAL for a null handle or
+ * pointer or nevt < 0, ME_EHIP if a launch fails. */
+me_status me_compute_weighted(me_handle h, const double* d_momenta, int64_t nevt, const double* d_factor,
+                              double* d_me, double* d_w, double* d_max, void* hip_stream);
+
 /* Multi-subprocess request: event e of the batch is evaluated with
  * handles[d_channel[e]] (e.g. the g g, u u~ and u~ u channels of
  * p p > t t~; the paper's Summary names p p -> t tbar + jets, whose

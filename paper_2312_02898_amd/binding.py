@@ -80,7 +80,7 @@ EXPORTS = [
     "me_good_helicities", "me_info", "me_destroy", "me_last_error",
     "me_server_create", "me_server_submit", "me_server_poll", "me_server_wait", "me_server_stats",
     "me_server_destroy", "me_max_weight", "me_rambo", "me_compute_channels", "me_server_times",
-    "me_workspace_bytes", "me_compute_channels_noalloc", "me_sample",
+    "me_workspace_bytes", "me_compute_channels_noalloc", "me_sample", "me_compute_weighted",
 ]
 
 # fixed device workspace of me_compute_channels_noalloc (ME_NOALLOC_SCRATCH_BYTES)
@@ -101,6 +101,7 @@ def lib():
         L.me_create.argtypes = [ctypes.c_char_p, P(me_sm_params), P(vp)]
         L.me_helicity_filter.argtypes = [vp]
         L.me_compute.argtypes = [vp, vp, i64, vp, vp]
+        L.me_compute_weighted.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp]
         L.me_compute_helicities.argtypes = [vp, vp, i64, vp, vp]
         L.me_good_helicities.argtypes = [vp, P(i32), i32, P(i32)]
         L.me_info.argtypes = [vp, P(me_info_t)]
@@ -176,6 +177,14 @@ def me_info(handle: int) -> dict:
 
 def me_destroy(handle: int) -> None:
     _check(lib().me_destroy(handle), "me_destroy")
+
+
+def me_compute_weighted(h, d_momenta: int, nevt: int, d_factor: int, d_me: int, d_w: int, d_max: int,
+                        stream: int = 0) -> None:
+    """me_compute with the weights d_w = max(d_me * d_factor, 0) (d_w may be
+    0) and their maximum *d_max formed in the same kernel (device pointers)."""
+    _check(lib().me_compute_weighted(h, d_momenta or None, int(nevt), d_factor or None, d_me or None, d_w or None,
+                                     d_max or None, stream or None), "me_compute_weighted")
 
 
 def me_max_weight(d_me: int, d_factor: int, nevt: int, d_w: int, d_max: int, stream: int = 0) -> None:

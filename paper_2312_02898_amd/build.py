@@ -70,7 +70,7 @@ def build(processes=None, jobs=None, verbose=True) -> str:
     from paper_2312_02898_amd.procgen import codegen
     procs = processes or PROCESSES
     srcs = codegen.generate(GEN, names=procs)
-    hdrs = [os.path.join(CSRC, f) for f in ("helas.hpp", "kernels.hpp", "me_types.h", "colour_mfma.hpp", "split.hpp")]
+    hdrs = [os.path.join(CSRC, f) for f in ("helas.hpp", "kernels.hpp", "me_types.h", "colour_mfma.hpp", "split.hpp", "epilogue.hpp")]
     table = os.path.join(GEN, "process_table.inc")
     # a part kernel of a split process, <name>__<form>_<j>.hip, shares <name>_proc.inc
     units = [(s, hdrs + [os.path.join(GEN, os.path.basename(s)[:-4].split("__")[0] + "_proc.inc")])

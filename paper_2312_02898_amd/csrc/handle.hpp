@@ -33,9 +33,11 @@ int64_t validate_momenta(const double* d_mom, int64_t nevt, int npar, hipStream_
 
 // me_compute with an optional device workspace for the processes that need
 // one (ws == NULL: the stream-ordered allocator; otherwise ws_bytes of it,
-// at least the handle's workspace(mode, nevt, nhel, ws_bytes)).
+// at least the handle's workspace(mode, nevt, nhel, ws_bytes)).  kp: the
+// kernel parameters to launch with (NULL: the handle's own), e.g. the
+// handle's with the weighted-event epilogue set.
 me_status compute_on(me_handle h, const double* d_momenta, int64_t nevt, double* d_me, hipStream_t s, void* ws,
-                     int64_t ws_bytes);
+                     int64_t ws_bytes, const MeParams* kp = nullptr);
 
 // Records code and message for me_last_error(); returns code.
 me_status set_error(me_status code, const std::string& msg);

@@ -12,6 +12,7 @@
 #include <stdint.h>
 
 #include "colour_mfma.hpp"
+#include "epilogue.hpp"
 #include "helas.hpp"
 #include "me_types.h"
 #include "split.hpp"
@@ -52,7 +53,7 @@ __global__ __launch_bounds__(256) void me_kernel(const double* __restrict__ mom,
     if (out_hel) out_hel[e * P::NHEL + hel] = q * (P::coupling_factor(prm) / P::CDEN);
     acc += q;
   }
-  if (out) out[e] = acc * (P::coupling_factor(prm) / (P::CDEN * P::IDEN));
+  if (out) store_me(prm, out, e, acc * (P::coupling_factor(prm) / (P::CDEN * P::IDEN)));
 }
 
 // Propagator factors and polarisation bases (eps_base) of one event in LDS,
@@ -140,7 +141,7 @@ __global__ __launch_bounds__(256) void me_kernel_kc(const double* __restrict__ m
     }
     acc += q;
   }
-  if (out) out[e] = acc * (P::coupling_factor(prm) / (P::CDEN * P::IDEN));
+  if (out) store_me(prm, out, e, acc * (P::coupling_factor(prm) / (P::CDEN * P::IDEN)));
 }
 
 // Per-event light-cone cache of the FP64 form in LDS (128-thread blocks):
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(128) void me_kernel_ldsjamp(const double* __restric
     if (out_hel) out_hel[e * P::NHEL + hel] = q * (P::coupling_factor(prm) / P::CDEN);
     acc += q;
   }
-  if (out) out[e] = acc * (P::coupling_factor(prm) / (P::CDEN * P::IDEN));
+  if (out) store_me(prm, out, e, acc * (P::coupling_factor(prm) / (P::CDEN * P::IDEN)));
 }
 
 // Mixed form with the colour sum on MFMA.  Every lane of a wave stays active
@@ -239,7 +240,7 @@ __global__ __launch_bounds__(256) void me_kernel_mfma(const double* __restrict__
     else
       acc += double(colour_sum_mfma<P::NCOLOR>(jamp, A, lds, lane));
   }
-  if (e < nevt) out[e] = acc * (P::coupling_factor(prm) / (P::CDEN * P::IDEN));
+  if (e < nevt) store_me(prm, out, e, acc * (P::coupling_factor(prm) / (P::CDEN * P::IDEN)));
 }
 
 // mode: ME_MODE_FP64; ME_MODE_MIXED (colour sum on the unit chosen for the

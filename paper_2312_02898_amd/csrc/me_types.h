@@ -16,6 +16,11 @@ struct MeParams {
   double mz, wz;    // Z mass and width
   double mt, wt;    // top mass and width (s-channel propagators)
   double wt_tchan;  // top width in t-channel propagators (0 in zero-width mode)
+  // weighted-event epilogue (w_fac NULL: none): w_out[e] = max(|M|^2_e w_fac[e], 0)
+  // when w_out is set, and their maximum as the bit pattern in *w_max
+  const double* w_fac;
+  double* w_out;
+  unsigned long long* w_max;
   int32_t nhel;     // number of helicity configurations in hel[]
   int32_t pad;
   uint8_t hel[128]; // helicity configurations: bit i = leg i has helicity +1

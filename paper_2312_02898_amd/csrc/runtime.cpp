@@ -112,7 +112,7 @@ namespace me {
 me_status set_error(me_status code, const std::string& msg) { return fail(code, msg); }
 
 me_status compute_on(me_handle h, const double* d_momenta, int64_t nevt, double* d_me, hipStream_t s, void* ws,
-                     int64_t ws_bytes) {
+                     int64_t ws_bytes, const MeParams* kp) {
   if (!h) return fail(ME_EINVAL, "me_compute: null handle");
   if (nevt < 0) return fail(ME_EINVAL, "me_compute: nevt < 0");
   if (nevt == 0) return ME_OK;
@@ -124,7 +124,8 @@ me_status compute_on(me_handle h, const double* d_momenta, int64_t nevt, double*
       return fail(ME_EINVAL, "me_compute: " + std::to_string(bad) +
                                  " events with non-finite components, negative energy or unbalanced momentum");
   }
-  const int rc = h->proc->launch(mode_of(h->params), d_momenta, nevt, d_me, nullptr, &h->kp, s, ws, ws_bytes);
+  const int rc = h->proc->launch(mode_of(h->params), d_momenta, nevt, d_me, nullptr, kp ? kp : &h->kp, s, ws,
+                                 ws_bytes);
   if (rc == -3)
     return fail(ws ? ME_EINVAL : ME_ENOMEM,
                 ws ? "me_compute: workspace too small" : "me_compute: no device memory for the workspace");
@@ -311,6 +312,29 @@ me_status me_helicity_filter(me_handle h) {
 
 me_status me_compute(me_handle h, const double* d_momenta, int64_t nevt, double* d_me, void* hip_stream) {
   return me::compute_on(h, d_momenta, nevt, d_me, static_cast<hipStream_t>(hip_stream), nullptr, 0);
+}
+
+namespace {
+__global__ void weight_max_clear(unsigned long long* bits) { *bits = 0ull; }
+}  // namespace
+
+me_status me_compute_weighted(me_handle h, const double* d_momenta, int64_t nevt, const double* d_factor,
+                              double* d_me, double* d_w, double* d_max, void* hip_stream) {
+  if (!h) return fail(ME_EINVAL, "me_compute_weighted: null handle");
+  if (nevt < 0) return fail(ME_EINVAL, "me_compute_weighted: nevt < 0");
+  if (!d_max || (nevt > 0 && (!d_momenta || !d_factor || !d_me)))
+    return fail(ME_EINVAL, "me_compute_weighted: null pointer");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  auto* bits = reinterpret_cast<unsigned long long*>(d_max);
+  // a fill kernel, not a memset: the call stays safe to capture in a graph
+  hipLaunchKernelGGL(weight_max_clear, dim3(1), dim3(1), 0, s, bits);
+  if (hipGetLastError() != hipSuccess) return fail(ME_EHIP, "me_compute_weighted: launch failed");
+  if (nevt == 0) return ME_OK;
+  me::MeParams kp = h->kp;
+  kp.w_fac = d_factor;
+  kp.w_out = d_w;
+  kp.w_max = bits;
+  return me::compute_on(h, d_momenta, nevt, d_me, s, nullptr, 0, &kp);
 }
 
 me_status me_workspace_bytes(me_handle h, int64_t nevt, int64_t* bytes) {

@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include "colour_mfma.hpp"
+#include "epilogue.hpp"
 #include "helas.hpp"
 
 namespace me {
@@ -183,7 +184,10 @@ __global__ __launch_bounds__(256) void me_colour_split_f16(const cx<float>* __re
     q += __shfl_xor(q, 32, 64);
     acc += double(ldexpf(q, 2 * ex));
   }
-  if (live && g == 0) out[e] = last ? acc * (P::coupling_factor(prm) / (P::CDEN * P::IDEN)) : acc;
+  if (live && g == 0) {
+    if (last) store_me(prm, out, e, acc * (P::coupling_factor(prm) / (P::CDEN * P::IDEN)));
+    else out[e] = acc;
+  }
 }
 
 // FP64 form on v_mfma_f64_16x16x4_f64.  Its result rows are interleaved:
@@ -249,7 +253,10 @@ __global__ __launch_bounds__(256) void me_colour_split_f64(const cx<double>* __r
     if (out_hel && live && g == 0) out_hel[e * P::NHEL + prm.hel[h0 + hc]] = q * f;
     acc += q;
   }
-  if (out && live && g == 0) out[e] = last ? acc * (f / P::IDEN) : acc;
+  if (out && live && g == 0) {
+    if (last) store_me(prm, out, e, acc * (f / P::IDEN));
+    else out[e] = acc;
+  }
 }
 
 // Events per chunk and the default workspace cap per call.  Without a
@@ -306,12 +313,13 @@ int run_split(const double* mom, int64_t nevt, double* out, double* out_hel, con
                    ne_pad, &prm);
       const dim3 cgrid(unsigned((ne + 63) / 64));
       const int first = h0 == 0 ? 1 : 0, last = h0 + nhc >= prm.nhel ? 1 : 0;
+      const MeParams cprm = epilogue_at(prm, e0);   // the last pass's epilogue sees this chunk
       if constexpr (sizeof(T) == 8)
         hipLaunchKernelGGL((me_colour_split_f64<P>), cgrid, dim3(256), 0, stream, X, ne, ne_pad, nhc, h0,
-                           out ? out + e0 : nullptr, out_hel ? out_hel + e0 * P::NHEL : nullptr, first, last, prm);
+                           out ? out + e0 : nullptr, out_hel ? out_hel + e0 * P::NHEL : nullptr, first, last, cprm);
       else
         hipLaunchKernelGGL((me_colour_split_f16<P>), cgrid, dim3(256), 0, stream, X, ne, ne_pad, nhc, out + e0,
-                           first, last, prm);
+                           first, last, cprm);
     }
   }
   const hipError_t err = hipGetLastError();
