@@ -61,11 +61,27 @@ def _compile(src, deps):
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr[-4000:]}")
+        # the object is cached under the digest of its inputs: if any input
+        # changed while it compiled, the object may hold other code than its
+        # name says, and it is not kept
+        if _digest([src] + deps, " ".join(FLAGS)) != tag:
+            os.remove(tmp)
+            raise RuntimeError(f"{src} or a header changed during its compile; build again")
         os.replace(tmp, obj)
     return obj
 
 
 def build(processes=None, jobs=None, verbose=True) -> str:
+    """Generate, compile and link; builds of one tree run one at a time (a
+    lock file), since they share csrc/gen and the object cache."""
+    import fcntl
+    os.makedirs(OBJ, exist_ok=True)
+    with open(os.path.join(OBJ, ".lock"), "w") as lock:
+        fcntl.flock(lock, fcntl.LOCK_EX)
+        return _build_locked(processes, jobs, verbose)
+
+
+def _build_locked(processes, jobs, verbose) -> str:
     sys.path.insert(0, ROOT)
     from paper_2312_02898_amd.procgen import codegen
     procs = processes or PROCESSES
