@@ -210,12 +210,23 @@ __global__ __launch_bounds__(128) void me_kernel_ldsjamp(const double* __restric
 
 // Mixed form with the colour sum on MFMA.  Every lane of a wave stays active
 // through the helicity loop (the MFMA needs the whole wave); lanes past the
-// end of the batch evaluate the last event again and do not store.
+// end of the batch evaluate the last event again and do not store.  The
+// kinematic cache of the vector-ALU form (propagator factors and polarisation
+// bases in LDS, once per event) is used when the process's FP32 schedule
+// reads one: with the colour staging, 126 KB of LDS per 256-lane block for
+// g g > t t~ g g.
 template <class P, bool F32OPS>
 __global__ __launch_bounds__(256) void me_kernel_mfma(const double* __restrict__ mom, int64_t nevt,
                                                       double* __restrict__ out, const MeParams prm) {
   constexpr int kLds = F32OPS ? kColourLds32Bytes : kColourLdsBytes;
   __shared__ __attribute__((aligned(16))) char lds_all[4 * kLds];
+  // the mixed form's kinematic cache (propagator factors and polarisation
+  // bases once per event), when the process's FP32 schedule reads one
+  constexpr int KR = P::KC_RE_F32, KC = P::KC_CX_F32, KE = P::KC_EPS_F32;
+  constexpr bool kCache = KR + KC + KE > 0;
+  __shared__ float kre[(kCache && KR > 0 ? KR : 1) * 256];
+  __shared__ cx<float> kcx[(kCache && KC > 0 ? KC : 1) * 256];
+  __shared__ float keps[5 * (kCache && KE > 0 ? KE : 1) * 256];
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int64_t e0 = int64_t(blockIdx.x) * blockDim.x + 64 * wave;
   if (e0 >= nevt) return;   // whole wave past the end (wave-uniform)
@@ -226,6 +237,8 @@ __global__ __launch_bounds__(256) void me_kernel_mfma(const double* __restrict__
   const ColourA32<P::NCOLOR> A32 = colour_a32<P::NCOLOR>(P::cmat(), lane);
   double p[P::NPAR][4];
   load_on_shell<P::MASSIVE>(mom + ec * (4 * P::NPAR), p, prm.mt);
+  LdsKinCache<float> dc{kre, kcx, keps, int(threadIdx.x)};
+  if constexpr (kCache) P::template den_fill_f32<float>(p, prm, dc);
   double acc = 0.0;
   for (int ih = 0; ih < prm.nhel; ++ih) {
 #pragma unroll
@@ -234,7 +247,12 @@ __global__ __launch_bounds__(256) void me_kernel_mfma(const double* __restrict__
       for (int c = 0; c < 4; ++c) asm volatile("" : "+v"(p[i][c]));
     const unsigned hel = prm.hel[ih];
     cx<float> jamp[P::NCOLOR];
-    P::template amplitudes<float>(p, hel, prm, jamp);
+    if constexpr (kCache) {
+      asm volatile("" : "+v"(dc.off));
+      P::template amplitudes<float>(p, hel, prm, jamp, dc);
+    } else {
+      P::template amplitudes<float>(p, hel, prm, jamp);
+    }
     if constexpr (F32OPS)
       acc += double(colour_sum_mfma32<P::NCOLOR>(jamp, A32, lds, lane));
     else
