@@ -200,7 +200,7 @@ me_status me_compute_channels(const me_handle* handles, int32_t nchannels, const
 
 /* Device workspace bytes that me_compute allocates (stream-ordered) for nevt
  * events of this handle: 0 for every process but "g g > t t~ g g g", whose
- * split form keeps its jamps in a workspace of up to 1 GiB per call.
+ * split form keeps its jamps in a workspace of up to 128 MiB per call.
  * ME_EINVAL for a null handle or pointer or nevt < 0. */
 me_status me_workspace_bytes(me_handle h, int64_t nevt, int64_t* bytes);
 
@@ -291,7 +291,7 @@ me_status me_sample(int64_t nevt, int32_t nfinal, const double* masses, double s
  * as integration channels emit them (continuous batching).  A request's
  * device footprint is its momenta, its results and the workspace its
  * process needs ("g g > t t~ g g g": the jamp workspace, capped per request
- * at a quarter of budget_bytes and at most 256 MiB), all carved from one
+ * at a quarter of budget_bytes and at most 128 MiB), all carved from one
  * device arena of budget_bytes allocated at creation; nothing is allocated
  * per request.  Requests are admitted in arrival order as stream slots and
  * arena memory free up; when the head of the queue waits for memory, at

@@ -66,10 +66,10 @@ struct HipExec {
 
 }  // namespace
 
-// Workspace cap per request: a quarter of the budget, at most 256 MiB (the
+// Workspace cap per request: a quarter of the budget, at most 128 MiB (the
 // split form then runs its helicities in several passes over a smaller
 // workspace; a request needs at least one helicity slot of it).
-constexpr int64_t kServeWorkspaceCap = int64_t(256) << 20;
+constexpr int64_t kServeWorkspaceCap = int64_t(128) << 20;
 
 struct me_server_s {
   HipExec exec;

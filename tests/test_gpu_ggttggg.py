@@ -6,7 +6,7 @@ every event (events above 1e-13 against the FP64 oracle re-evaluated with
 the long-double oracle, fp64_bar.py), mixed form
 median <= 1e-5 and max <= 1e-3.  The oracle takes about 0.2 s per event on
 one core, so element-wise checks use a few hundred events; the chunked
-launch (events beyond one chunk of 2^17, helicities in several workspace
+launch (events beyond one chunk of 2^14, helicities in several workspace
 slices) is checked on sampled events and against the same events in a small
 batch.
 """
@@ -22,7 +22,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 NAME = CONFIGS["ggttggg"][0]
-CHUNK = 1 << 17
+CHUNK = 1 << 14
 
 
 @pytest.fixture(scope="module")
