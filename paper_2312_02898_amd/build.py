@@ -1,7 +1,9 @@
 """Build the gfx950 engine library in-tree.
 
 1. the process compiler writes csrc/gen/<process>.hip and process_table.inc;
-2. hipcc compiles every generated kernel file and the runtime for gfx950;
+2. hipcc compiles every generated kernel file and the runtime for gfx950,
+   and each unit's device assembly is checked for half-spilled register
+   pairs (isa_check.py), a miscompile that yields wrong values silently;
 3. the objects are linked into libme_mi355x.so next to this file.
 
 Run as ``python -m paper_2312_02898_amd.build`` (also called by the graft
@@ -68,7 +70,33 @@ def _compile(src, deps):
             os.remove(tmp)
             raise RuntimeError(f"{src} or a header changed during its compile; build again")
         os.replace(tmp, obj)
+    _check_device_code(src, obj)
     return obj
+
+
+def _check_device_code(src, obj):
+    """Compile the unit's device code to assembly once more and reject it if
+    the compiler spilled half of a 64-bit register pair (isa_check): such a
+    kernel computes wrong values with no fault.  The result is cached next
+    to the object."""
+    from . import isa_check
+    stamp = obj + ".isa-ok"
+    if os.path.exists(stamp):
+        return
+    asm = obj + ".s.tmp"
+    cmd = [HIPCC] + FLAGS + ["-S", "--offload-device-only", src, "-o", asm]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc -S failed for {src}:\n{r.stderr[-4000:]}")
+    with open(asm) as f:
+        text = f.read()
+    os.remove(asm)
+    bad = isa_check.half_reloads(text)
+    if bad:
+        raise RuntimeError(f"{src}: the device compiler reloads half of a spilled 64-bit register pair "
+                           f"(the kernel would compute wrong values); change the schedule:\n" + "\n".join(bad[:5]))
+    with open(stamp, "w"):
+        pass
 
 
 def build(processes=None, jobs=None, verbose=True) -> str:
@@ -109,10 +137,10 @@ def _build_locked(processes, jobs, verbose) -> str:
         raise RuntimeError(f"link failed:\n{r.stderr[-4000:]}")
     os.replace(tmp, LIB)
     # drop stale objects
-    keep = set(objs)
+    keep = set(objs) | {o + ".isa-ok" for o in objs}
     for f in os.listdir(OBJ):
         p = os.path.join(OBJ, f)
-        if p not in keep and f.endswith(".o"):
+        if p not in keep and (f.endswith(".o") or f.endswith(".isa-ok")):
             os.remove(p)
     if verbose:
         print(f"built {LIB}")
