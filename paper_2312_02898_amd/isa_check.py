@@ -10,8 +10,11 @@ g g > t t~ g g g whose C++ is exact on the host; the same source compiled
 with scratch-only spills is exact.
 
 `half_reloads` finds that signature: a 4-byte reload into register r_N
-followed, before its mate in an even-aligned pair (r_{N xor 1}) is written,
-by a read of a register range that holds both.  Straight-line
+that is not accompanied by a restore of its mate in the even-aligned pair
+(r_{N xor 1}: no write to it among the few instructions before the reload,
+where the compiler puts the restore of a pair saved half to scratch and half
+to a spare register), followed, before the mate is written, by a read of a
+register range that holds both.  Straight-line
 scan per function (branches are not followed), so it can report a case that
 control flow rules out; the build treats every report as an error.
 """
@@ -50,6 +53,25 @@ def _regs(tokens):
     return out
 
 
+def _mate_restored_before(lines, i, kind, mate, window=8):
+    """True if one of the `window` instructions before line i writes the mate
+    register: the compiler restores a pair whose halves were saved in two
+    places (scratch and a spare register) with adjacent instructions."""
+    seen = 0
+    for j in range(i - 1, -1, -1):
+        op, dst, _ = _operands(lines[j])
+        if op is None:
+            if re.match(r"^[A-Za-z_.][\w.$]*:", lines[j]):
+                break   # block boundary
+            continue
+        if any(r[0] == kind and r[1] <= mate <= r[2] for r in _regs(dst)):
+            return True
+        seen += 1
+        if seen >= window:
+            break
+    return False
+
+
 def half_reloads(asm: str) -> list[str]:
     """Reports (function, line number, text) of every half reload."""
     lines = asm.split("\n")
@@ -63,6 +85,8 @@ def half_reloads(asm: str) -> list[str]:
             continue
         kind, n = m[1], int(m[2])
         mate = n ^ 1   # 64-bit register tuples are even-aligned
+        if _mate_restored_before(lines, i, kind, mate):
+            continue   # a pair spilled half to scratch, half to a register, and restored whole
         for j in range(i + 1, len(lines)):
             l2 = lines[j]
             if re.match(r"^[A-Za-z_][\w.$]*:", l2) and not l2.startswith(".L"):

@@ -900,7 +900,7 @@ MIXED_MFMA = set()
 # the wavefunction budget (FP64 dwords), the number of jamp accumulators a
 # lane holds at once, the number of parts and (optional) whether the
 # accumulators live in LDS instead of registers.
-SPLIT = {"ggttggg": {"f64": (288, 36, 12, True), "f32": (384, 40, 8)}}
+SPLIT = {"ggttggg": {"f64": (288, 36, 12, True), "f32": (384, 56, 8)}}
 
 
 def split_program(p: Program, cfg: dict, budget=None) -> Program:

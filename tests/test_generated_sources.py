@@ -38,5 +38,5 @@ def test_shipped_schedule_parameters():
                                             "ggttgg": (320, 4)}
     assert program.DEFAULT_SCHEDULE_F32 == {"eemumu": (256, 4), "ggtt": (256, 4), "ggttg": (384, 1),
                                             "ggttgg": (448, 2)}
-    assert program.SPLIT == {"ggttggg": {"f64": (288, 36, 12, True), "f32": (384, 40, 8)}}
+    assert program.SPLIT == {"ggttggg": {"f64": (288, 36, 12, True), "f32": (384, 56, 8)}}
     assert program.SHARE_HALF == {"ggttg": False, "ggttgg": False, "ggttggg": True}

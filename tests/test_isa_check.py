@@ -51,6 +51,10 @@ FN = "_Zkernel:\n"
     ("\tscratch_load_dword v10, off, off offset:8\n\tv_add_f32_e32 v0, v10, v2\n\tv_mov_b32_e32 v10, v1\n", 0),
     # stored as part of a pair: a read of the pair
     ("\tscratch_load_dword v10, off, off offset:8\n\tglobal_store_dwordx2 v[4:5], v[10:11], off\n", 1),
+    # a pair saved half to scratch and half to a spare register, restored by
+    # adjacent instructions (what the compiler does right)
+    ("\tv_accvgpr_read_b32 v11, a207\n\tscratch_load_dword v10, off, off offset:84\n"
+     "\tv_lshl_add_u64 v[66:67], v[10:11], 3, s[0:1]\n", 0),
 ])
 def test_synthetic_cases(body, n):
     assert len(isa_check.half_reloads(FN + body)) == n
