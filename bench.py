@@ -26,42 +26,50 @@ sys.path.insert(0, ROOT)
 FP32_VECTOR_PEAK = 157.3e12   # MI355X fp32 vector (packed) FLOP/s
 FP64_VECTOR_PEAK = 78.6e12    # MI355X fp64 vector FLOP/s
 
-# HBM traffic per launch of the gg -> t t~ g g mixed kernels at 2^20 events,
+# Memory traffic per launch of the gg -> t t~ g g kernels at 2^20 events,
 # from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs (KiB per
-# dispatch), scaled by what the same counters read for a 1 GiB device copy
-# (FETCH_SIZE 0.5 GiB, WRITE_SIZE 1 GiB: scales 2 and 1).  Valid only for
-# the kernel source they were taken on (digest below); null otherwise.
+# dispatch, what leaves the L2), scaled by what the same counters read for a
+# 1 GiB device copy (FETCH_SIZE 0.5 GiB, WRITE_SIZE 1 GiB: scales 2 and 1).
+# Valid only for the kernel source they were taken on (digest below); null
+# otherwise.
 PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 MEASURED_TRAFFIC = {
-    "valu": {"digest": "f2e9ba516e7a9fbd", "fetch_kib": 99034, "write_kib": 8192},
-    "mfma_f16_hilo": {"digest": "e29b5c956a83b294", "fetch_kib": 99014, "write_kib": 8192},
+    "valu": {"digest": "73e9a19e921d018c", "fetch_kib": 99030, "write_kib": 8192},
+    "mfma_f16_hilo": {"digest": "056195a2b18fbafb", "fetch_kib": 99035, "write_kib": 8192},
+    "fp64": {"digest": "2b07ee9521cf45e3", "fetch_kib": 8752198, "write_kib": 34080111},
 }
 
 
+def _function(text, signature):
+    a = text.index(signature)
+    return text[a:text.index("\n  }\n", a)]
+
+
 def kernel_digest(variant):
-    """Digest of the sources that make the gg -> t t~ g g mixed kernel: its
-    generated FP32 amplitude function, colour form and propagator-cache fill,
-    the kernel and device headers and the compiler flags."""
+    """Digest of the sources that make one gg -> t t~ g g kernel: its
+    generated amplitude function, colour sum and per-event cache fill, the
+    kernel template, the device headers it includes and the compiler flags."""
     import hashlib
     from paper_2312_02898_amd import build as pb
     csrc = os.path.join(ROOT, "paper_2312_02898_amd", "csrc")
     with open(os.path.join(csrc, "gen", "ggttgg_proc.inc")) as f:
         inc = f.read()
-    a = inc.index("static void amplitudes_f32")
-    b = inc.index("\n  }\n", a)
-    h = hashlib.sha256(inc[a:b].encode())
-    if variant == "valu":
-        for fn in ("static T colour_sum", "static void den_fill_f32"):
-            a = inc.index(fn)
-            h.update(inc[a:inc.index("\n  }\n", a)].encode())
+    fp64 = variant == "fp64"
+    h = hashlib.sha256(_function(inc, "static void amplitudes_f64" if fp64 else "static void amplitudes_f32").encode())
+    fns = {"valu": ("static T colour_sum", "static void den_fill_f32"),
+           "mfma_f16_hilo": ("static void den_fill_f32",),
+           "fp64": ("static T colour_sum", "static void lc_fill")}[variant]
+    for fn in fns:
+        h.update(_function(inc, fn).encode())
     # the kernel template itself (not the rest of kernels.hpp: dispatch code
     # does not change the kernel's binary)
     with open(os.path.join(csrc, "kernels.hpp")) as fh:
         kh = fh.read()
-    name = "void me_kernel_kc(" if variant == "valu" else "void me_kernel_mfma("
+    name = {"valu": "void me_kernel_kc(", "mfma_f16_hilo": "void me_kernel_mfma(",
+            "fp64": "void me_kernel_ldsjamp("}[variant]
     a = kh.rindex("template", 0, kh.index(name))
     h.update(kh[a:kh.index("\n}\n", a)].encode())
-    files = ("helas.hpp", "me_types.h") + (("colour_mfma.hpp",) if variant != "valu" else ())
+    files = ("helas.hpp", "me_types.h", "epilogue.hpp") + (("colour_mfma.hpp",) if variant == "mfma_f16_hilo" else ())
     for f in files:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
@@ -74,11 +82,6 @@ def measured_traffic(variant):
     if not m or m["digest"] != kernel_digest(variant):
         return None
     return (m["fetch_kib"] * PMC_FETCH_SCALE + m["write_kib"] * PMC_WRITE_SCALE) * 1024.0
-
-
-def log(msg):
-    """Progress of the run on stderr (the JSON line alone goes to stdout)."""
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def time_kernel(me, m, out, steps, warmup):
@@ -228,12 +231,13 @@ def main():
                                   "max": float(rel.max()), "events": n},
         "roofline": {"bound": "alu", "achieved": ach32 / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
                      "unit": "TFLOP/s", "frac": ach32 / FP32_VECTOR_PEAK, "traffic": measured_traffic(best),
-                     "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "traffic_unit": "bytes per launch past the L2 (rocprofv3 2 x FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "algorithmic_bytes": n * info["bytes_per_event"],
                      "kernel": variants[best]["kernel"],
                      "flops_per_event": flops_evt, "kernel_ms": t_launch32 * 1e3},
         "roofline_fp64": {"bound": "alu", "achieved": ach64 / 1e12, "peak": FP64_VECTOR_PEAK / 1e12,
-                          "unit": "TFLOP/s", "frac": ach64 / FP64_VECTOR_PEAK,
+                          "unit": "TFLOP/s", "frac": ach64 / FP64_VECTOR_PEAK, "traffic": measured_traffic("fp64"),
+                          "algorithmic_bytes": n * info["bytes_per_event"],
                           "kernel": "me_kernel_ldsjamp<Proc_ggttgg, double>", "kernel_ms": t_launch64 * 1e3},
     }
 
