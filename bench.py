@@ -499,6 +499,10 @@ def main():
             ev = sum(x.shape[0] for x in moms)
             q = np.array([t[0] for t in qs])
             sv = np.array([t[1] for t in qs])
+            # small requests: estimated work at most the server's large-request
+            # threshold (2e10 flop), the class kept apart from long requests
+            fpe = {nm: B.me_info(handles[nm])["flops_per_event"] for nm in names}
+            small = np.array([fpe[p_] * m.shape[0] <= 2e10 for p_, m in zip(procs, moms)])
             per = {}
             for nm in names:
                 idx = [k for k, p_ in enumerate(procs) if p_ == nm]
@@ -508,17 +512,24 @@ def main():
             return {"offered_load": load, "offered_rate_hz": rate, "budget_bytes": budget,
                     "requests": len(moms), "p50_latency_ms": float(np.median(lat) * 1e3),
                     "p99_latency_ms": float(np.quantile(lat, 0.99) * 1e3),
+                    "small_requests": int(small.sum()),
+                    "p50_latency_ms_small": float(np.median(lat[small]) * 1e3),
+                    "p99_latency_ms_small": float(np.quantile(lat[small], 0.99) * 1e3),
+                    "p99_latency_ms_large": float(np.quantile(lat[~small], 0.99) * 1e3),
                     "queue_ms": {"p50": float(np.median(q) * 1e3), "p99": float(np.quantile(q, 0.99) * 1e3)},
                     "service_ms": {"p50": float(np.median(sv) * 1e3), "p99": float(np.quantile(sv, 0.99) * 1e3)},
                     "throughput_ME_s": ev / wall, "failed": int((status != 0).sum()),
-                    "peak_bytes_in_use": st["peak_bytes_in_use"], "admissions_past_waiting_head": st["bypassed"],
+                    "peak_bytes_in_use": st["peak_bytes_in_use"], "admissions_past_waiting_head": st["bypassed"], "small_passing_large_head": st["passed_large"],
                     "per_process": per}
 
         log("serving")
         runs = [serve(0.7, 4 << 30), serve(0.5, 4 << 30), serve(0.9, 4 << 30), serve(0.7, 256 << 20)]
         head = runs[0]
         rec["serving"] = {"requests": head["requests"], "p50_latency_ms": head["p50_latency_ms"],
-                          "p99_latency_ms": head["p99_latency_ms"], "throughput_ME_s": head["throughput_ME_s"],
+                          "p99_latency_ms": head["p99_latency_ms"],
+                          "p99_latency_ms_small": head["p99_latency_ms_small"],
+                          "p99_latency_ms_large": head["p99_latency_ms_large"],
+                          "throughput_ME_s": head["throughput_ME_s"],
                           "failed": sum(r["failed"] for r in runs), "processes": names,
                           "standalone_mixed_ME_s": cap, "runs": runs}
         for h in handles.values():

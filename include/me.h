@@ -296,7 +296,13 @@ me_status me_sample(int64_t nevt, int32_t nfinal, const double* masses, double s
  * per request.  Requests are admitted in arrival order as stream slots and
  * arena memory free up; when the head of the queue waits for memory, at
  * most 16 later requests that fit may pass it before the queue is strictly
- * in order again.  Admitted work on different slots overlaps on the device.
+ * in order again.  Requests whose estimated work (flops of the process x
+ * events) exceeds 2e10 are large: they may hold at most half of the slots,
+ * small requests pass a large head that waits for such a slot, and a large
+ * request above 2e11 runs in pieces of 16384 events with one piece's kernels
+ * queued at a time, so a small request neither queues behind long ones nor
+ * waits behind their whole kernel sequence on a shared hardware queue.
+ * Admitted work on different slots overlaps on the device.
  * Host buffers: the server stages momenta to device memory and results
  * back.  Handles must be filtered before submission and stay alive while
  * their requests are in flight.
@@ -309,6 +315,7 @@ typedef struct {
   int64_t bytes_in_use, peak_bytes_in_use;
   int32_t active_slots, queued;
   int64_t bypassed;         /* admissions past a head that waited for memory */
+  int64_t passed_large;     /* admissions past a large head that waited for a slot */
 } me_server_stats_t;
 
 /* n_slots HIP streams (1..64), budget_bytes of device memory for requests. */

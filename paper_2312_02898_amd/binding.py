@@ -71,6 +71,7 @@ class me_server_stats_t(ctypes.Structure):
         ("active_slots", ctypes.c_int32),
         ("queued", ctypes.c_int32),
         ("bypassed", ctypes.c_int64),
+        ("passed_large", ctypes.c_int64),
     ]
 
 

@@ -17,6 +17,12 @@
 
 namespace {
 
+// A request above this estimated work runs in pieces of whole 2^14-event
+// chunks (the split form's), one piece's kernels in its stream at a time:
+// about 20 ms of g g > t t~ g g g; everything else runs whole.
+constexpr int64_t kServePieceFlops = int64_t(200) * 1000 * 1000 * 1000;
+constexpr int64_t kServePieceAlign = int64_t(1) << 14;
+
 struct HipExec {
   int device = 0;
   char* d_arena = nullptr;
@@ -24,6 +30,41 @@ struct HipExec {
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> events;
   std::vector<int> launch_ok;
+  // a request in flight on a slot: its region and the next event to launch
+  struct InFlight {
+    me::Request req;
+    int64_t off = 0, next = 0, piece = 0;
+  };
+  std::vector<InFlight> inflight;
+
+  // Events per piece: the whole request, or whole chunks worth about
+  // kServePieceFlops.  Pieces keep the hardware queue that a slot's stream
+  // shares with other slots from holding a long request's whole kernel
+  // sequence, behind which a small request would wait.
+  static int64_t piece_events(const me::Request& r) {
+    if (r.cost <= kServePieceFlops || r.nevt <= kServePieceAlign) return r.nevt;
+    const int64_t per_event = r.cost / r.nevt > 0 ? r.cost / r.nevt : 1;
+    int64_t n = (kServePieceFlops / per_event + kServePieceAlign - 1) / kServePieceAlign * kServePieceAlign;
+    if (n < kServePieceAlign) n = kServePieceAlign;
+    return n < r.nevt ? n : r.nevt;
+  }
+  // enqueues events [f.next, f.next + n) and, after the last piece, the copy
+  // of the results; records the slot's event
+  bool enqueue_piece(int slot) {
+    InFlight& f = inflight[size_t(slot)];
+    const me::Request& r = f.req;
+    const int64_t n = r.nevt - f.next < f.piece ? r.nevt - f.next : f.piece;
+    double* d_mom = reinterpret_cast<double*>(d_arena + f.off) + f.next * 4 * r.npar;
+    double* d_out = reinterpret_cast<double*>(d_arena + f.off + out_offset(r)) + f.next;
+    void* d_ws = r.ws_bytes > 0 ? d_arena + f.off + ws_offset(r) : nullptr;
+    hipStream_t s = streams[size_t(slot)];
+    bool ok = me::compute_on(static_cast<me_handle>(r.handle), d_mom, n, d_out, s, d_ws, r.ws_bytes) == ME_OK;
+    f.next += n;
+    if (ok && f.next == r.nevt)
+      ok = hipMemcpyAsync(h_arena + f.off + out_offset(r), d_arena + f.off + out_offset(r), size_t(r.nevt) * 8,
+                          hipMemcpyDeviceToHost, s) == hipSuccess;
+    return ok && hipEventRecord(events[size_t(slot)], s) == hipSuccess;
+  }
 
   static int64_t out_offset(const me::Request& r) { return r.nevt * int64_t(32) * r.npar; }
   // the request's region: momenta, results, then its process's workspace
@@ -34,15 +75,14 @@ struct HipExec {
     launch_ok[slot] = 0;
     const size_t in_bytes = size_t(r.nevt) * 32 * r.npar;
     std::memcpy(h_arena + off, r.h_mom, in_bytes);
-    double* d_mom = reinterpret_cast<double*>(d_arena + off);
-    double* d_out = reinterpret_cast<double*>(d_arena + off + out_offset(r));
-    void* d_ws = r.ws_bytes > 0 ? d_arena + off + ws_offset(r) : nullptr;
     hipStream_t s = streams[slot];
-    bool ok = hipMemcpyAsync(d_mom, h_arena + off, in_bytes, hipMemcpyHostToDevice, s) == hipSuccess;
-    ok = ok && me::compute_on(static_cast<me_handle>(r.handle), d_mom, r.nevt, d_out, s, d_ws, r.ws_bytes) == ME_OK;
-    ok = ok && hipMemcpyAsync(h_arena + off + out_offset(r), d_out, size_t(r.nevt) * 8, hipMemcpyDeviceToHost,
-                              s) == hipSuccess;
-    ok = ok && hipEventRecord(events[slot], s) == hipSuccess;
+    InFlight& f = inflight[size_t(slot)];
+    f.req = r;
+    f.off = off;
+    f.next = 0;
+    f.piece = piece_events(r);
+    bool ok = hipMemcpyAsync(d_arena + off, h_arena + off, in_bytes, hipMemcpyHostToDevice, s) == hipSuccess;
+    ok = ok && enqueue_piece(slot);
     if (!ok) {
       // the core frees the region at once: nothing queued above may still
       // be reading or writing it
@@ -52,9 +92,18 @@ struct HipExec {
     launch_ok[slot] = 1;
     return true;
   }
+  // the slot's work is done when its last piece and the copy of the results
+  // have completed; a completed earlier piece starts the next one
   bool done(int slot) {
-    hipError_t e = hipEventQuery(events[slot]);
-    return e != hipErrorNotReady;
+    if (hipEventQuery(events[slot]) == hipErrorNotReady) return false;
+    InFlight& f = inflight[size_t(slot)];
+    if (!launch_ok[slot] || f.next >= f.req.nevt) return true;
+    if (!enqueue_piece(slot)) {
+      (void)hipStreamSynchronize(streams[slot]);
+      launch_ok[slot] = 0;   // finish() reports the failure
+      return true;
+    }
+    return false;
   }
   bool finish(int slot, me::Request& r, int64_t off) {
     if (!launch_ok[slot]) return false;
@@ -70,6 +119,10 @@ struct HipExec {
 // split form then runs its helicities in several passes over a smaller
 // workspace; a request needs at least one helicity slot of it).
 constexpr int64_t kServeWorkspaceCap = int64_t(128) << 20;
+
+// Requests above this estimated work (flop) are large: about 1 ms of the
+// g g > t t~ g g g split form or of 14 000 g g > t t~ g g events.
+constexpr int64_t kServeLargeFlops = int64_t(20) * 1000 * 1000 * 1000;
 
 struct me_server_s {
   HipExec exec;
@@ -96,6 +149,7 @@ me_status me_server_create(int64_t budget_bytes, int32_t n_slots, me_server* out
     if (ok) ex.events.push_back(ev);
   }
   ex.launch_ok.assign(n_slots, 0);
+  ex.inflight.assign(size_t(n_slots), HipExec::InFlight{});
   if (!ok) {
     for (auto st : ex.streams) (void)hipStreamDestroy(st);
     for (auto ev : ex.events) (void)hipEventDestroy(ev);
@@ -105,7 +159,7 @@ me_status me_server_create(int64_t budget_bytes, int32_t n_slots, me_server* out
     return ME_EHIP;
   }
   s->ws_cap = budget_bytes / 4 < kServeWorkspaceCap ? budget_bytes / 4 : kServeWorkspaceCap;
-  s->core.reset(new me::ServerCore<HipExec>(ex, budget_bytes, n_slots));
+  s->core.reset(new me::ServerCore<HipExec>(ex, budget_bytes, n_slots, 16, kServeLargeFlops));
   *out = s;
   return ME_OK;
 }
@@ -123,6 +177,9 @@ me_status me_server_submit(me_server s, me_handle h, const double* h_momenta, in
   r.npar = info.npar;
   // the device workspace of the request's process counts in its footprint
   r.ws_bytes = nevt > 0 ? h->proc->workspace(me::mode_of(h->params), nevt, h->kp.nhel, s->ws_cap) : 0;
+  // estimated device work: the process's algorithmic flops per helicity x
+  // good helicities x events
+  r.cost = nevt * int64_t(h->proc->flops_per_hel) * h->kp.nhel;
   int rc = s->core->submit(r, ticket);
   if (rc == -1) return ME_EINVAL;
   if (rc == -3) return ME_ENOMEM;
@@ -174,6 +231,7 @@ me_status me_server_stats(me_server s, me_server_stats_t* st) {
   st->active_slots = x.active_slots;
   st->queued = x.queued;
   st->bypassed = x.bypassed;
+  st->passed_large = x.passed_large;
   return ME_OK;
 }
 

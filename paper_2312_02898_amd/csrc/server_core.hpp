@@ -10,7 +10,10 @@
 // memory, not for a slot), later requests that fit may pass it, but at most
 // max_bypass of them per head: after that the queue is strictly in order
 // until the head is admitted, so the head's wait is bounded by the service
-// of the work already admitted.  Requests admitted while others are in
+// of the work already admitted.  With a cost threshold, large requests (by
+// estimated device work) may hold at most half of the slots, the rest being
+// kept for small ones, and small requests pass a large head that waits for
+// such a slot: a small request then never queues behind long ones.  Requests admitted while others are in
 // flight run concurrently on their own slots.  The executor does the device
 // work; the core only does bookkeeping, so it is independent of HIP and can
 // be driven by a fake executor on the CPU.
@@ -45,6 +48,8 @@ struct Request {
   int64_t nevt = 0;
   int32_t npar = 0;
   int64_t ws_bytes = 0;            // device workspace of the request's process (set by the submitter)
+  int64_t cost = 0;                // estimated device work (flop; set by the submitter)
+  bool large = false;              // cost above the server's threshold (set at submission)
   int64_t bytes = 0;               // device footprint: momenta, results and workspace
   std::chrono::steady_clock::time_point t_submit;
   std::chrono::steady_clock::time_point t_admit;   // slot and memory granted, work launched
@@ -104,6 +109,7 @@ class Arena {
 struct ServerStats {
   int64_t submitted = 0, completed = 0, failed = 0, rejected = 0, events_completed = 0;
   int64_t bypassed = 0;   // admissions past a head that waited for memory
+  int64_t passed_large = 0;   // admissions past a large head that waited for a large-request slot
   int64_t bytes_in_use = 0, peak_bytes_in_use = 0;
   int32_t active_slots = 0, queued = 0;
 };
@@ -115,8 +121,17 @@ class ServerCore {
   // request's region
   static int64_t io_bytes(const Request& r) { return r.nevt * (int64_t(32) * r.npar + 8); }
 
-  ServerCore(Exec& ex, int64_t budget, int nslots, int max_bypass = 16)
-      : ex_(ex), arena_(budget), slots_(nslots), max_bypass_(max_bypass), stop_(false) {
+  // large_cost > 0 splits requests into small and large by their cost: at
+  // most nslots - small_slots large requests are in flight at once (small_slots
+  // < 0: half of the slots), so small requests always find a slot instead of
+  // queueing behind long ones; large requests take slots from the low end,
+  // small ones from the high end.
+  ServerCore(Exec& ex, int64_t budget, int nslots, int max_bypass = 16, int64_t large_cost = 0,
+             int small_slots = -1)
+      : ex_(ex), arena_(budget), slots_(nslots), max_bypass_(max_bypass), large_cost_(large_cost), stop_(false) {
+    if (small_slots < 0) small_slots = nslots / 2;
+    if (small_slots > nslots - 1) small_slots = nslots - 1;
+    large_cap_ = large_cost > 0 ? nslots - small_slots : nslots;
     loop_ = std::thread([this] { run(); });
   }
   ~ServerCore() { shutdown(); }
@@ -125,6 +140,7 @@ class ServerCore {
   int submit(Request r, int64_t* ticket) {
     if (r.nevt <= 0 || !r.h_mom || !r.h_out || r.npar <= 0 || r.ws_bytes < 0) return -1;
     r.bytes = Arena::round(Arena::round(io_bytes(r)) + r.ws_bytes);
+    r.large = large_cost_ > 0 && r.cost > large_cost_;
     std::lock_guard<std::mutex> lk(mu_);
     if (r.bytes > arena_.capacity()) {
       ++st_.rejected;
@@ -194,6 +210,7 @@ class ServerCore {
     t.status = status;
     t.latency_s = std::chrono::duration<double>(now - s.req.t_submit).count();
     t.queue_s = std::chrono::duration<double>(s.req.t_admit - s.req.t_submit).count();
+    if (s.req.large) --large_active_;
     if (status == 0) {
       ++st_.completed;
       st_.events_completed += s.req.nevt;
@@ -221,32 +238,45 @@ class ServerCore {
       progress = true;
     }
     while (!queue_.empty()) {
-      int free_slot = -1;
-      for (size_t i = 0; i < slots_.size(); ++i)
-        if (!slots_[i].busy) { free_slot = int(i); break; }
-      if (free_slot < 0) break;
-      // the head if it fits; else, while the head may still be passed, the
-      // first later request that fits
+      bool any_free = false;
+      for (auto& sl : slots_) any_free |= !sl.busy;
+      if (!any_free) break;
+      // the head if it may start now; else the first later request that may
+      // (past a head that waits for memory at most max_bypass times; past a
+      // large head that waits for a large-request slot freely: that costs
+      // the head nothing, small requests never take those slots)
       size_t pick = 0;
-      int64_t off = arena_.alloc(queue_.front().bytes);
+      int64_t off = -1;
+      const bool head_class_ok = class_ok(queue_.front());
+      if (head_class_ok) off = arena_.alloc(queue_.front().bytes);
       if (off < 0) {
-        if (head_bypassed_ >= max_bypass_) break;   // strictly in order until the head is admitted
+        if (head_class_ok && head_bypassed_ >= max_bypass_) break;   // strictly in order until the head is admitted
+        // past a large head that waits for a slot, only into the slots
+        // reserved for small requests: the head's slots stay for it
+        if (!head_class_ok && free_slot_in(large_cap_, int(slots_.size())) < 0) break;
         for (size_t q = 1; q < queue_.size() && q <= kBypassWindow; ++q) {
+          if (!class_ok(queue_[q]) || (!head_class_ok && queue_[q].large)) continue;
           off = arena_.alloc(queue_[q].bytes);
           if (off >= 0) { pick = q; break; }
         }
         if (off < 0) break;
-        ++head_bypassed_;
-        ++st_.bypassed;
+        if (head_class_ok) {
+          ++head_bypassed_;
+          ++st_.bypassed;
+        } else {
+          ++st_.passed_large;
+        }
       } else {
         head_bypassed_ = 0;
       }
+      const int free_slot = slot_for(queue_[pick]);
       Slot& s = slots_[free_slot];
       s.req = queue_[pick];
       s.req.t_admit = std::chrono::steady_clock::now();
       queue_.erase(queue_.begin() + std::ptrdiff_t(pick));
       s.busy = true;
       s.off = off;
+      if (s.req.large) ++large_active_;
       st_.peak_bytes_in_use = std::max(st_.peak_bytes_in_use, arena_.used());
       Request r = s.req;
       lk.unlock();
@@ -288,13 +318,35 @@ class ServerCore {
     }
   }
 
+  // a request may start now as far as its class goes (a free slot of the
+  // right kind exists: checked by the caller and slot_for)
+  bool class_ok(const Request& r) const {
+    if (r.large) return large_active_ < large_cap_ && free_slot_in(0, large_cap_) >= 0;
+    return true;
+  }
+  int free_slot_in(int lo, int hi) const {
+    for (int i = lo; i < hi; ++i)
+      if (!slots_[size_t(i)].busy) return i;
+    return -1;
+  }
+  // large requests: the lowest free slot; small ones: the highest
+  int slot_for(const Request& r) const {
+    if (r.large) return free_slot_in(0, large_cap_);
+    for (int i = int(slots_.size()) - 1; i >= 0; --i)
+      if (!slots_[size_t(i)].busy) return i;
+    return -1;
+  }
+
   // later requests looked at when the head does not fit
-  static constexpr size_t kBypassWindow = 64;
+  static constexpr size_t kBypassWindow = 1024;
 
   Exec& ex_;
   Arena arena_;
   std::vector<Slot> slots_;
   int max_bypass_;
+  int64_t large_cost_;
+  int large_cap_ = 0;       // large requests in flight at most
+  int large_active_ = 0;
   int head_bypassed_ = 0;   // requests admitted past the current head
   std::deque<Request> queue_;
   std::map<int64_t, TicketState> tickets_;

@@ -116,9 +116,80 @@ int run_footprint(const std::string& sc) {
   return 0;
 }
 
+// Large and small requests by estimated cost ("classes"): 8 slots, cost
+// threshold 1000; 10 large requests (cost 5000, 150 ms) submitted first,
+// then 30 small ones (cost 10, 5 ms).  At most 4 large ones run at once
+// (half of the slots kept for small ones), the small ones start without
+// waiting for the large ones, and every request completes.
+int run_classes() {
+  const int nslots = 8;
+  FakeExec ex(nslots);
+  std::vector<int64_t> costs;
+  for (int i = 0; i < 10; ++i) { costs.push_back(5000); ex.service_of.push_back(0.15); }
+  for (int i = 0; i < 30; ++i) { costs.push_back(10); ex.service_of.push_back(0.005); }
+  const int nreq = int(costs.size());
+  std::vector<std::vector<double>> in(nreq), out(nreq);
+  std::vector<int64_t> tickets;
+  std::vector<double> queue(nreq);
+  std::vector<int> status(nreq);
+  std::vector<int> live_large(nreq, 0);
+  me::ServerStats st;
+  int max_large = 0;
+  {
+    me::ServerCore<FakeExec> core(ex, int64_t(1) << 24, nslots, 16, 1000);
+    for (int i = 0; i < nreq; ++i) {
+      in[i].assign(100 * 16, 0.0);
+      for (int64_t e = 0; e < 100; ++e) in[i][e * 16] = double(i * 1000 + e);
+      out[i].assign(100, -1.0);
+      me::Request r;
+      r.h_mom = in[i].data(); r.h_out = out[i].data(); r.nevt = 100; r.npar = 4; r.cost = costs[i];
+      int64_t t = -1;
+      if (core.submit(r, &t) != 0) return 2;
+      tickets.push_back(t);
+    }
+    // sample how many large requests run at once
+    for (int k = 0; k < 400; ++k) {
+      int large = 0;
+      {
+        std::lock_guard<std::mutex> lk(ex.mu);
+        for (int sl = 0; sl < nslots; ++sl) {
+          const int64_t t = ex.slot_ticket[size_t(sl)];
+          if (t >= 1 && t <= 10 && ex.concurrent > 0) {
+            const double age = std::chrono::duration<double>(clk::now() - ex.t0[size_t(sl)]).count();
+            if (age < ex.service_of[size_t(t - 1)]) ++large;
+          }
+        }
+      }
+      if (large > max_large) max_large = large;
+      std::this_thread::sleep_for(std::chrono::milliseconds(1));
+    }
+    for (int i = 0; i < nreq; ++i) {
+      me::TicketState ts; bool known;
+      bool ok = core.wait(tickets[i], 30.0, &ts, &known);
+      status[i] = ok ? ts.status : 999;
+      queue[i] = ts.queue_s;
+    }
+    st = core.stats();
+  }
+  int correct = 1;
+  for (int i = 0; i < nreq; ++i)
+    for (size_t e = 0; e < out[i].size(); ++e)
+      if (out[i][e] != 2.0 * in[i][e * 16]) correct = 0;
+  printf("{\"scenario\": \"classes\", \"correct\": %d, \"completed\": %lld, \"failed\": %lld, "
+         "\"passed_large\": %lld, \"max_large\": %d, \"max_concurrent\": %d, \"status\": [",
+         correct, (long long)st.completed, (long long)st.failed, (long long)st.passed_large, max_large,
+         ex.max_concurrent.load());
+  for (int i = 0; i < nreq; ++i) printf("%s%d", i ? ", " : "", status[i]);
+  printf("], \"queue\": [");
+  for (int i = 0; i < nreq; ++i) printf("%s%.6f", i ? ", " : "", queue[i]);
+  printf("]}\n");
+  return 0;
+}
+
 int main(int argc, char** argv) {
   std::string sc = argc > 1 ? argv[1] : "basic";
   if (sc == "workspace" || sc == "bypass") return run_footprint(sc);
+  if (sc == "classes") return run_classes();
   int nslots = sc == "memory" ? 8 : 4;
   int64_t budget = sc == "memory" ? 300000 : (1 << 20);   // "memory": about 2 requests fit
   int nreq = sc == "overlap" ? 8 : 12;

@@ -100,3 +100,20 @@ def test_small_requests_pass_a_waiting_head_boundedly(harness):
     # small requests that passed were taken in arrival order
     small = [t for t in order if t > 4]
     assert small == sorted(small)
+
+
+def test_small_requests_do_not_queue_behind_large_ones(harness):
+    """Ten large requests (150 ms each) submitted before thirty small ones
+    (5 ms) on 8 slots with a cost threshold: at most four large ones run at
+    once, the small ones start at once on the slots kept for them (passing
+    the large ones that wait for a slot), and every request completes."""
+    r = run(harness, "classes")
+    assert r["completed"] == 40 and r["failed"] == 0 and r["correct"] == 1
+    assert all(s == 0 for s in r["status"])
+    assert r["max_large"] <= 4
+    small_queue = r["queue"][10:]
+    # a small request waits at most for another small one on the reserved slots
+    assert max(small_queue) < 0.1, max(small_queue)
+    assert r["passed_large"] >= 1
+    # the large ones that waited started once a large slot freed (about 150 ms)
+    assert max(r["queue"][:10]) >= 0.1
