@@ -84,6 +84,11 @@ def measured_traffic(variant):
     return (m["fetch_kib"] * PMC_FETCH_SCALE + m["write_kib"] * PMC_WRITE_SCALE) * 1024.0
 
 
+def log(msg):
+    """Progress of the run on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def time_kernel(me, m, out, steps, warmup):
     import torch
     for _ in range(warmup):
