@@ -430,9 +430,9 @@ def main():
     # long-double oracle, the bar being 1e-12 against it on each)
     if not args.no_cpu:
         import oracle
-        subsets = {"eemumu": 16384, "ggtt": 1 << 16, "ggttg": 1 << 13, "ggttgg": 1 << 11, "ggttggg": 192,
-                   "uutt": 1 << 16, "uxutt": 1 << 16, "uuttg": 1 << 13, "uxuttg": 1 << 13, "ugttu": 1 << 13,
-                   "guttu": 1 << 13, "uxgttux": 1 << 13, "guxttux": 1 << 13,
+        subsets = {"eemumu": 16384, "ggtt": 1 << 19, "ggttg": 1 << 16, "ggttgg": 1 << 14, "ggttggg": 192,
+                   "uutt": 1 << 19, "uxutt": 1 << 19, "uuttg": 1 << 14, "uxuttg": 1 << 14, "ugttu": 1 << 14,
+                   "guttu": 1 << 14, "uxgttux": 1 << 14, "guxttux": 1 << 14,
                    "uuttgg": 1 << 11, "ugttug": 1 << 11, "ggttuux": 1 << 11, "uuttuux": 1 << 11,
                    "uuttuu": 1 << 11}
         errs = {}
