@@ -121,3 +121,24 @@ def test_over_budget_and_invalid(handles):
         assert st["rejected"] == 1 and st["submitted"] == 0
     finally:
         B.me_server_destroy(srv)
+
+
+def test_large_requests_run_in_pieces(handles):
+    """g g > t t~ g g g requests above 2e11 flop (here 40 000 and 16 385
+    events) run in pieces of 16 384 events, one piece's kernels queued at a
+    time, with small requests arriving meanwhile: every result equals the
+    same request evaluated in one call, bit for bit."""
+    from paper_2312_02898_amd import binding as B
+    from paper_2312_02898_amd.inputs import CONFIGS, process_events
+    from paper_2312_02898_amd.serving import run_stream
+    rng = np.random.default_rng(3)
+    procs = ["ggttggg", "ggtt", "ggttgg", "ggttggg", "eemumu", "ggttg", "ggtt", "ggttgg"]
+    sizes = [40000, 300, 2000, 16385, 256, 1000, 5000, 700]
+    moms = [process_events(CONFIGS[p][0], n, CONFIGS[p][1], 100 + i) for i, (p, n) in enumerate(zip(procs, sizes))]
+    arr = np.cumsum(rng.exponential(0.002, size=len(procs))) - 0.002
+    print(f"[serving pieces] sizes={sizes}", flush=True)
+    lat, status, outs, wall, st = run_stream(handles, np.maximum(arr, 0.0), procs, moms, budget_bytes=1 << 30,
+                                             n_slots=8)
+    assert (status == 0).all() and st["completed"] == len(procs)
+    for name, m, o in zip(procs, moms, outs):
+        assert np.array_equal(o, _alone(B, handles[name], m)), name
