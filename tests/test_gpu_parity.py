@@ -194,3 +194,31 @@ def test_debug_validation(B, dev, monkeypatch):
             _run(me, m, dev)
         assert e.value.status == B.ME_EINVAL
     me.close()
+
+
+def test_batch_beyond_2gib_of_momenta(oracle_lib, B, dev):
+    """2^24 + 13 g g > t t~ events (2.1 GB of momenta: byte offsets past
+    2^31) generated on the device, both forms; sampled events, the last ones
+    among them, against the oracle."""
+    n = (1 << 24) + 13
+    print(f"[beyond 2 GiB] ggtt nevt={n}", flush=True)
+    m = torch.empty((n, 4, 4), dtype=torch.float64, device=dev)
+    B.me_rambo(n, [173.0, 173.0], 1500.0, 77, m.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    rng = np.random.default_rng(5)
+    idx = np.unique(np.concatenate([rng.choice(n, size=200, replace=False), np.arange(n - 40, n)]))
+    sel = torch.from_numpy(idx).to(dev)
+    mom = m[sel].cpu().numpy()
+    ref = oracle_lib.me("g g > t t~", mom)
+    for precision in ("fp64", "mixed"):
+        me = _me(B, "ggtt", precision)
+        out = me(m)
+        torch.cuda.synchronize()
+        assert bool(torch.isfinite(out).all()) and bool((out > 0).all())
+        got = out[sel].cpu().numpy()
+        if precision == "fp64":
+            _check_fp64(oracle_lib, "g g > t t~", mom, got, ref)
+        else:
+            rel = _rel(got, ref)
+            assert np.median(rel) <= 1e-5 and rel.max() <= 1e-3
+        me.close()
+        del out
