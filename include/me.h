@@ -85,10 +85,15 @@ typedef enum {
   ME_MIXED_MFMA32 = 3, /* as ME_MIXED with the colour sum on MFMA with FP32
                         operands (exact FP32 jamps and colour matrix, no
                         hi+lo split) for 6..32 colour flows */
-  ME_MIXED_MFMA16 = 4 /* as ME_MIXED with the colour sum on MFMA with FP16
+  ME_MIXED_MFMA16 = 4, /* as ME_MIXED with the colour sum on MFMA with FP16
                         hi+lo jamps, exact FP16 colour matrix and FP32
                         accumulation, for 6..32 colour flows and the split
                         form */
+  ME_MIXED_MFMABF16 = 5 /* as ME_MIXED with the colour sum on MFMA with BF16
+                        hi+lo jamps (16 significant bits), exact BF16 colour
+                        matrix and FP32 accumulation, for 6..32 colour flows
+                        (other processes: vector ALU; the split form keeps
+                        FP16 hi+lo, its colour matrix needing 9 bits) */
 } me_precision;
 
 /* Standard-Model inputs.  me_default_params() fills the benchmark values

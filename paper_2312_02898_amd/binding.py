@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libme_mi355x.so")
 
 ME_OK, ME_EINVAL, ME_EPROCESS, ME_ENOMEM, ME_EHIP, ME_ENOTSUP, ME_EBUSY = 0, -1, -2, -3, -4, -5, -6
-ME_FP64, ME_MIXED, ME_MIXED_VALU, ME_MIXED_MFMA32, ME_MIXED_MFMA16 = 0, 1, 2, 3, 4
+ME_FP64, ME_MIXED, ME_MIXED_VALU, ME_MIXED_MFMA32, ME_MIXED_MFMA16, ME_MIXED_MFMABF16 = 0, 1, 2, 3, 4, 5
 
 
 class MeError(RuntimeError):

@@ -1,21 +1,31 @@
-// Colour sum on MFMA for the mixed form (one event per lane, 64 events per wave).
+// Colour sum on MFMA for the mixed form (one event per lane, 64 events per wave),
+// with hi+lo jamps in FP16 or BF16 (below) or with FP32 operands (further down).
 //
 // For each helicity the wave holds jamp[NCOLOR] (FP32 complex) per lane.
 // q_e = x_e^T C x_e + y_e^T C y_e (x = Re jamp, y = Im jamp, C the integer
 // colour matrix) is evaluated as the dense product  D' = C X^T  on
-// v_mfma_f32_16x16x32_f16 (M = colours, N = 64 events in 4 tiles, K =
-// colours, padded to 32), followed by each lane's dot of its own row of D
+// v_mfma_f32_16x16x32_f16 or _bf16 (M = colours, N = 64 events in 4 tiles,
+// K = colours, padded to 32), followed by each lane's dot of its own row of D
 // with its own jamps:
-//   * per (event, helicity) a power-of-two scale 2^-s brings max|jamp| below 1
-//     (exact), then X = hi + lo with hi = f16(x), lo = f16(x - hi): about 22
-//     significant bits;
+//   * FP16: per (event, helicity) a power-of-two scale 2^-s brings max|jamp|
+//     below 1 (exact), then X = hi + lo with hi = f16(x), lo = f16(x - hi):
+//     about 22 significant bits;
+//   * BF16: hi = bf16(x), lo = bf16(x - hi), both rounded to nearest even
+//     (x - hi is exact in FP32), so |x - hi - lo| <= 2^-8 |x - hi| <=
+//     2^-16 |x|: 16 significant bits; BF16 has the exponent range of FP32,
+//     so no scale is needed;
 //   * C has at most 10 significant bits (integers <= 512 for 4 gluons), so it
-//     is exact in FP16 and C*hi, C*lo are exact in the FP32 accumulator;
+//     is exact in FP16; the colour matrices of 6..32 flows have at most 7
+//     and are exact in BF16 (8 bits); C*hi and C*lo are exact in the FP32
+//     accumulator;
 //   * C is the A operand, loaded once per kernel into registers; X reaches
 //     the B operand layout through LDS (8 consecutive colours of one event per
 //     lane, one 128-bit load); a lane's D' fragment is 4 consecutive colours
 //     of one event, stored with one 128-bit write; each lane then reads its own
-//     row back.
+//     row back.  The staging holds only the colours there are (rows of KP =
+//     8 ceil(NC/8) colours, products of MP = 16 ceil(NC/16)): lane groups
+//     whose K slots are all padding take zero B operands without reading LDS,
+//     and the smaller footprint leaves room for more waves per CU.
 // MFMA operand layout (16x16x32, wave64): lane l supplies A[l%16][8(l/16)+j]
 // and B[8(l/16)+j][l%16] for j = 0..7, and receives D[4(l/16)+i][l%16] for
 // i = 0..3.  Only the pairing of A's and B's K slots matters for the product,
@@ -28,10 +38,15 @@
 namespace me {
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float float4v __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float4v mfma16x16x32(half8 a, half8 b, float4v c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ float4v mfma16x16x32(bf16x8 a, bf16x8 b, float4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
 __device__ __forceinline__ void wave_lds_sync() {
@@ -40,93 +55,126 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Per-wave LDS: hi and lo planes [64 events][32 colours] of halves (8 KB) and
-// the product rows [64 events][32 colours] of floats (8 KB), reused for the
-// real and the imaginary part.
-constexpr int kColourLdsBytes = 2 * 64 * 32 * 2 + 64 * 32 * 4;
-
+// Staging of NC colour flows: per wave, hi and lo planes [64 events][KP] of
+// 2-byte elements and the product rows [64 events][MP] of floats, reused for
+// the real and the imaginary part (g g > t t~ g g: 14 KB; 6 flows: 6 KB).
 template <int NC>
+struct ColourTile {
+  static constexpr int KP = 8 * ((NC + 7) / 8), MP = 16 * ((NC + 15) / 16);
+  static constexpr int kLdsBytes = 2 * 64 * KP * 2 + 64 * MP * 4;
+};
+
+// hi+lo element types: FP16 with the per-event power-of-two scale (its
+// exponent range is narrow), BF16 without
+template <class H>
+struct HiLo;
+template <>
+struct HiLo<_Float16> {
+  typedef half8 vec;
+  static constexpr bool kScale = true;
+};
+template <>
+struct HiLo<__bf16> {
+  typedef bf16x8 vec;
+  static constexpr bool kScale = false;
+};
+
+template <int NC, class H = _Float16>
 struct ColourA {
-  half8 a[2];   // A operand (colour matrix) for colour tiles 0 and 1
+  typename HiLo<H>::vec a[2];   // A operand (colour matrix) for colour tiles 0 and 1
 };
 
 // A operand registers from the integer colour matrix (row-major NC x NC):
 // lane l holds C[16m + l%16][8(l/16) + j].
-template <int NC>
-__device__ __forceinline__ ColourA<NC> colour_a(const int* cmat, int lane) {
-  ColourA<NC> r;
+template <int NC, class H = _Float16>
+__device__ __forceinline__ ColourA<NC, H> colour_a(const int* cmat, int lane) {
+  ColourA<NC, H> r;
 #pragma unroll
   for (int m = 0; m < 2; ++m) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int row = 16 * m + lane % 16, k = 8 * (lane / 16) + j;
-      r.a[m][j] = (row < NC && k < NC) ? _Float16(float(cmat[row * NC + k])) : _Float16(0.0f);
+      r.a[m][j] = H((row < NC && k < NC) ? float(cmat[row * NC + k]) : 0.0f);
     }
   }
   return r;
 }
 
 // Returns sum_kl C_kl Re(conj(jamp_k) jamp_l) for this lane's event; every
-// lane of the wave must call it (uniform control flow).
-template <int NC>
-__device__ __forceinline__ float colour_sum_mfma(const cx<float> (&jamp)[NC], const ColourA<NC>& A,
+// lane of the wave must call it (uniform control flow).  lds_wave holds
+// ColourTile<NC>::kLdsBytes.
+template <int NC, class H = _Float16>
+__device__ __forceinline__ float colour_sum_mfma(const cx<float> (&jamp)[NC], const ColourA<NC, H>& A,
                                                  void* lds_wave, int lane) {
   static_assert(NC <= 32, "MFMA colour sum handles up to 32 colour flows");
-  _Float16* phi = reinterpret_cast<_Float16*>(lds_wave);
-  _Float16* plo = phi + 64 * 32;
-  float* drow = reinterpret_cast<float*>(plo + 64 * 32);
-  float m = 0.f;
-#pragma unroll
-  for (int k = 0; k < NC; ++k) m = fmaxf(m, fmaxf(fabsf(jamp[k].r), fabsf(jamp[k].i)));
+  typedef typename HiLo<H>::vec V;
+  constexpr int KP = ColourTile<NC>::KP, MP = ColourTile<NC>::MP;
+  H* phi = reinterpret_cast<H*>(lds_wave);
+  H* plo = phi + 64 * KP;
+  float* drow = reinterpret_cast<float*>(plo + 64 * KP);
   int ex = 0;
-  (void)frexpf(m, &ex);
+  if constexpr (HiLo<H>::kScale) {
+    float m = 0.f;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) m = fmaxf(m, fmaxf(fabsf(jamp[k].r), fabsf(jamp[k].i)));
+    (void)frexpf(m, &ex);
+  }
   const int g = lane / 16, c16 = lane % 16;
+  const bool live = 8 * g < KP;   // this lane group's K slots hold colours
   float q = 0.f;
 #pragma unroll
   for (int ri = 0; ri < 2; ++ri) {
-    // this lane's event row: scaled hi/lo halves, 8 colours per 128-bit store
+    // this lane's event row: hi/lo pairs, 8 colours per 128-bit store (the
+    // padding colours are zeros: they meet zero columns of C, and must not
+    // be NaN)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      half8 h, l;
+    for (int c = 0; c < KP / 8; ++c) {
+      V h, l;
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int k = 8 * c + j;
-        const float x = k < NC ? ldexpf(ri ? jamp[k < NC ? k : 0].i : jamp[k < NC ? k : 0].r, -ex) : 0.f;
-        const _Float16 hx = _Float16(x);
+        float x = k < NC ? (ri ? jamp[k < NC ? k : 0].i : jamp[k < NC ? k : 0].r) : 0.f;
+        if constexpr (HiLo<H>::kScale) x = ldexpf(x, -ex);
+        const H hx = H(x);
         h[j] = hx;
-        l[j] = _Float16(x - float(hx));
+        l[j] = H(x - float(hx));
       }
-      *reinterpret_cast<half8*>(&phi[lane * 32 + 8 * c]) = h;
-      *reinterpret_cast<half8*>(&plo[lane * 32 + 8 * c]) = l;
+      *reinterpret_cast<V*>(&phi[lane * KP + 8 * c]) = h;
+      *reinterpret_cast<V*>(&plo[lane * KP + 8 * c]) = l;
     }
     wave_lds_sync();
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const half8 bhi = *reinterpret_cast<const half8*>(&phi[(16 * t + c16) * 32 + 8 * g]);
-      const half8 blo = *reinterpret_cast<const half8*>(&plo[(16 * t + c16) * 32 + 8 * g]);
+      V bhi = {}, blo = {};
+      if (live) {
+        bhi = *reinterpret_cast<const V*>(&phi[(16 * t + c16) * KP + 8 * g]);
+        blo = *reinterpret_cast<const V*>(&plo[(16 * t + c16) * KP + 8 * g]);
+      }
 #pragma unroll
-      for (int mt = 0; mt < 2; ++mt) {
-        if (16 * mt >= NC) continue;
+      for (int mt = 0; mt < MP / 16; ++mt) {
         float4v d = {0.f, 0.f, 0.f, 0.f};
         d = mfma16x16x32(A.a[mt], bhi, d);
         d = mfma16x16x32(A.a[mt], blo, d);
         // d[i] = (C X^T)[16mt + 4g + i][16t + c16]
-        *reinterpret_cast<float4v*>(&drow[(16 * t + c16) * 32 + 16 * mt + 4 * g]) = d;
+        *reinterpret_cast<float4v*>(&drow[(16 * t + c16) * MP + 16 * mt + 4 * g]) = d;
       }
     }
     wave_lds_sync();
 #pragma unroll
     for (int c = 0; c < (NC + 3) / 4; ++c) {
-      const float4v d = *reinterpret_cast<const float4v*>(&drow[lane * 32 + 4 * c]);
+      const float4v d = *reinterpret_cast<const float4v*>(&drow[lane * MP + 4 * c]);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int k = 4 * c + i;
-        if (k < NC) q += ldexpf(ri ? jamp[k].i : jamp[k].r, -ex) * d[i];
+        if (k < NC) {
+          const float x = ri ? jamp[k].i : jamp[k].r;
+          q += (HiLo<H>::kScale ? ldexpf(x, -ex) : x) * d[i];
+        }
       }
     }
     wave_lds_sync();   // the next pass overwrites the planes and rows
   }
-  return ldexpf(q, 2 * ex);
+  return HiLo<H>::kScale ? ldexpf(q, 2 * ex) : q;
 }
 
 // ---------------------------------------------------------------------------

@@ -22,6 +22,7 @@ inline int mode_of(const me_sm_params& p) {
          : p.precision == ME_MIXED_VALU   ? ME_MODE_MIXED_VALU
          : p.precision == ME_MIXED_MFMA32 ? ME_MODE_MIXED_MFMA32
          : p.precision == ME_MIXED_MFMA16 ? ME_MODE_MIXED_MFMA16
+         : p.precision == ME_MIXED_MFMABF16 ? ME_MODE_MIXED_MFMABF16
                                           : ME_MODE_FP64;
 }
 

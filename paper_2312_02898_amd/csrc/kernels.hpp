@@ -213,12 +213,15 @@ __global__ __launch_bounds__(128) void me_kernel_ldsjamp(const double* __restric
 // end of the batch evaluate the last event again and do not store.  The
 // kinematic cache of the vector-ALU form (propagator factors and polarisation
 // bases in LDS, once per event) is used when the process's FP32 schedule
-// reads one: with the colour staging, 126 KB of LDS per 256-lane block for
-// g g > t t~ g g.
-template <class P, bool F32OPS>
-__global__ __launch_bounds__(256) void me_kernel_mfma(const double* __restrict__ mom, int64_t nevt,
-                                                      double* __restrict__ out, const MeParams prm) {
-  constexpr int kLds = F32OPS ? kColourLds32Bytes : kColourLdsBytes;
+// reads one: with the colour staging, 115 KB of LDS per 256-lane block for
+// g g > t t~ g g.  OPS: the colour sum's operands, FP16 hi+lo jamps, FP32
+// jamps or BF16 hi+lo jamps (colour_mfma.hpp).
+enum { kMfmaF16HiLo = 0, kMfmaF32 = 1, kMfmaBf16HiLo = 2 };
+
+template <class P, int OPS>
+__device__ __forceinline__ void me_mfma_body(const double* __restrict__ mom, int64_t nevt, double* __restrict__ out,
+                                             const MeParams& prm) {
+  constexpr int kLds = OPS == kMfmaF32 ? kColourLds32Bytes : ColourTile<P::NCOLOR>::kLdsBytes;
   __shared__ __attribute__((aligned(16))) char lds_all[4 * kLds];
   // the mixed form's kinematic cache (propagator factors and polarisation
   // bases once per event), when the process's FP32 schedule reads one
@@ -235,6 +238,7 @@ __global__ __launch_bounds__(256) void me_kernel_mfma(const double* __restrict__
   void* lds = lds_all + wave * kLds;
   const ColourA<P::NCOLOR> A = colour_a<P::NCOLOR>(P::cmat(), lane);
   const ColourA32<P::NCOLOR> A32 = colour_a32<P::NCOLOR>(P::cmat(), lane);
+  const ColourA<P::NCOLOR, __bf16> Ab = colour_a<P::NCOLOR, __bf16>(P::cmat(), lane);
   double p[P::NPAR][4];
   load_on_shell<P::MASSIVE>(mom + ec * (4 * P::NPAR), p, prm.mt);
   LdsKinCache<float> dc{kre, kcx, keps, int(threadIdx.x)};
@@ -253,18 +257,35 @@ __global__ __launch_bounds__(256) void me_kernel_mfma(const double* __restrict__
     } else {
       P::template amplitudes<float>(p, hel, prm, jamp);
     }
-    if constexpr (F32OPS)
+    if constexpr (OPS == kMfmaF32)
       acc += double(colour_sum_mfma32<P::NCOLOR>(jamp, A32, lds, lane));
+    else if constexpr (OPS == kMfmaBf16HiLo)
+      acc += double(colour_sum_mfma<P::NCOLOR, __bf16>(jamp, Ab, lds, lane));
     else
       acc += double(colour_sum_mfma<P::NCOLOR>(jamp, A, lds, lane));
   }
   if (e < nevt) store_me(prm, out, e, acc * (P::coupling_factor(prm) / (P::CDEN * P::IDEN)));
 }
 
+// FP16 hi+lo (F32OPS false) or FP32 (true) colour-sum operands
+template <class P, bool F32OPS>
+__global__ __launch_bounds__(256) void me_kernel_mfma(const double* __restrict__ mom, int64_t nevt,
+                                                      double* __restrict__ out, const MeParams prm) {
+  me_mfma_body<P, F32OPS ? kMfmaF32 : kMfmaF16HiLo>(mom, nevt, out, prm);
+}
+
+// BF16 hi+lo colour-sum operands
+template <class P>
+__global__ __launch_bounds__(256) void me_kernel_mfma_bf16(const double* __restrict__ mom, int64_t nevt,
+                                                           double* __restrict__ out, const MeParams prm) {
+  me_mfma_body<P, kMfmaBf16HiLo>(mom, nevt, out, prm);
+}
+
 // mode: ME_MODE_FP64; ME_MODE_MIXED (colour sum on the unit chosen for the
-// process, P::MIXED_MFMA); ME_MODE_MIXED_VALU, ME_MODE_MIXED_MFMA16 or
-// ME_MODE_MIXED_MFMA32 (vector ALU, FP16 hi+lo or FP32 MFMA; the MFMA forms
-// for 6 to 32 colour flows, the vector ALU otherwise).  out_hel (FP64 only) receives the
+// process, P::MIXED_MFMA); ME_MODE_MIXED_VALU, ME_MODE_MIXED_MFMA16,
+// ME_MODE_MIXED_MFMA32 or ME_MODE_MIXED_MFMABF16 (vector ALU, FP16 hi+lo, FP32
+// or BF16 hi+lo MFMA; the MFMA forms for 6 to 32 colour flows, the vector ALU
+// otherwise).  out_hel (FP64 only) receives the
 // colour-summed |M_h|^2 of every listed helicity, [nevt][NHEL].
 template <class P>
 int launch(int mode, const double* mom, int64_t nevt, double* out, double* out_hel, const MeParams& prm,
@@ -288,16 +309,20 @@ int launch(int mode, const double* mom, int64_t nevt, double* out, double* out_h
                          out_hel, prm);
     }
   } else if (((mode == ME_MODE_MIXED && P::MIXED_MFMA) || mode == ME_MODE_MIXED_MFMA16 ||
-              mode == ME_MODE_MIXED_MFMA32) && P::NCOLOR >= 6 && P::NCOLOR <= 32) {
+              mode == ME_MODE_MIXED_MFMA32 || mode == ME_MODE_MIXED_MFMABF16) && P::NCOLOR >= 6 &&
+             P::NCOLOR <= 32) {
     if (out_hel || !out) return -1;
-    if (mode != ME_MODE_MIXED_MFMA32)
-      hipLaunchKernelGGL((me_kernel_mfma<P, false>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
-                         prm);
-    else
+    if (mode == ME_MODE_MIXED_MFMA32)
       hipLaunchKernelGGL((me_kernel_mfma<P, true>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
                          prm);
+    else if (mode == ME_MODE_MIXED_MFMABF16)
+      hipLaunchKernelGGL((me_kernel_mfma_bf16<P>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
+                         prm);
+    else
+      hipLaunchKernelGGL((me_kernel_mfma<P, false>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
+                         prm);
   } else if (mode == ME_MODE_MIXED || mode == ME_MODE_MIXED_VALU || mode == ME_MODE_MIXED_MFMA32 ||
-             mode == ME_MODE_MIXED_MFMA16) {
+             mode == ME_MODE_MIXED_MFMA16 || mode == ME_MODE_MIXED_MFMABF16) {
     if (out_hel) return -1;
     if constexpr (P::F32_LDS_JAMPS) {
       const int64_t nb = (nevt + 127) / 128;

@@ -6,7 +6,8 @@
 
 namespace me {
 
-enum { ME_MODE_FP64 = 0, ME_MODE_MIXED = 1, ME_MODE_MIXED_VALU = 2, ME_MODE_MIXED_MFMA32 = 3, ME_MODE_MIXED_MFMA16 = 4 };
+enum { ME_MODE_FP64 = 0, ME_MODE_MIXED = 1, ME_MODE_MIXED_VALU = 2, ME_MODE_MIXED_MFMA32 = 3, ME_MODE_MIXED_MFMA16 = 4,
+       ME_MODE_MIXED_MFMABF16 = 5 };
 
 // Kernel argument block (passed by value; lives in the kernarg segment).
 struct MeParams {

@@ -226,7 +226,7 @@ me_status me_create(const char* process, const me_sm_params* p, me_handle* out) 
   const me::ProcessEntry* e = find_process(process);
   if (!e) return fail(ME_EPROCESS, std::string("me_create: unknown process '") + process + "'");
   if (p->precision != ME_FP64 && p->precision != ME_MIXED && p->precision != ME_MIXED_VALU &&
-      p->precision != ME_MIXED_MFMA32 && p->precision != ME_MIXED_MFMA16)
+      p->precision != ME_MIXED_MFMA32 && p->precision != ME_MIXED_MFMA16 && p->precision != ME_MIXED_MFMABF16)
     return fail(ME_EINVAL, "me_create: bad precision");
   if (!(p->alpha_em > 0) || !(p->alpha_s > 0) || !(p->sin2_thetaw > 0 && p->sin2_thetaw < 1) || !(p->mz > 0) ||
       !(p->wz >= 0) || !(p->mt >= 0) || !(p->wt >= 0) || p->filter_nevt < 1 || !(p->filter_sqrt_s > 0))

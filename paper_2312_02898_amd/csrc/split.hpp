@@ -344,7 +344,7 @@ int launch_split(int mode, const double* mom, int64_t nevt, double* out, double*
   if (mode == ME_MODE_FP64)
     return run_split<P, double>(mom, nevt, out, out_hel, prm, stream, ws, ws_bytes, parts64, n64);
   if (mode != ME_MODE_MIXED && mode != ME_MODE_MIXED_VALU && mode != ME_MODE_MIXED_MFMA32 &&
-      mode != ME_MODE_MIXED_MFMA16)
+      mode != ME_MODE_MIXED_MFMA16 && mode != ME_MODE_MIXED_MFMABF16)
     return -1;
   if (out_hel || !out) return -1;
   return run_split<P, float>(mom, nevt, out, nullptr, prm, stream, ws, ws_bytes, parts32, n32);

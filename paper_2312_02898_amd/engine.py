@@ -78,14 +78,16 @@ class ChannelMix:
 class MatrixElement:
     """One process handle.  precision: "fp64", "mixed" (colour sum on the
     unit measured fastest for the process), "mixed_mfma16" (FP16 hi+lo MFMA),
-    "mixed_mfma32" (FP32 MFMA) or "mixed_valu" (vector ALU)."""
+    "mixed_mfma32" (FP32 MFMA), "mixed_mfma_bf16" (BF16 hi+lo MFMA) or
+    "mixed_valu" (vector ALU)."""
 
     def __init__(self, process: str, precision: str = "fp64", filter_helicities: bool = True, **params):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the matrix-element engine has no CPU path")
         prm = B.me_default_params(**params)
         prm.precision = {"fp64": B.ME_FP64, "mixed": B.ME_MIXED, "mixed_valu": B.ME_MIXED_VALU,
-                         "mixed_mfma32": B.ME_MIXED_MFMA32, "mixed_mfma16": B.ME_MIXED_MFMA16}[precision]
+                         "mixed_mfma32": B.ME_MIXED_MFMA32, "mixed_mfma16": B.ME_MIXED_MFMA16,
+                         "mixed_mfma_bf16": B.ME_MIXED_MFMABF16}[precision]
         self.process = PROCESS_NAMES.get(process, process)
         self.handle = B.me_create(self.process, prm)
         if filter_helicities:

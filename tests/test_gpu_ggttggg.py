@@ -64,7 +64,8 @@ def test_fp64_matches_oracle(oracle_lib, dev, small):
     _check_fp64(oracle_lib, mom, gpu, ref)
 
 
-@pytest.mark.parametrize("precision", ["mixed", "mixed_valu"])
+# every mixed form of the split process sums colours on FP16 hi+lo MFMA
+@pytest.mark.parametrize("precision", ["mixed", "mixed_valu", "mixed_mfma_bf16"])
 def test_mixed_matches_oracle(dev, small, precision):
     mom, ref = small
     print(f"[ggttggg {precision}] nevt={mom.shape[0]}", flush=True)

@@ -88,7 +88,7 @@ def test_fp64_full_size_sampled(oracle_lib, B, dev, proc):
     _check_fp64(oracle_lib, name, mom[idx], gpu[idx], ref)
 
 
-@pytest.mark.parametrize("precision", ["mixed", "mixed_valu", "mixed_mfma16", "mixed_mfma32"])
+@pytest.mark.parametrize("precision", ["mixed", "mixed_valu", "mixed_mfma16", "mixed_mfma32", "mixed_mfma_bf16"])
 @pytest.mark.parametrize("proc", PROCS)
 def test_mixed_precision_error(oracle_lib, B, dev, proc, precision):
     mom = config_events(proc, NCHECK[proc])
@@ -162,10 +162,13 @@ def test_abi_errors(B, dev):
     B.me_destroy(h)
 
 
-@pytest.mark.parametrize("variant,med,mx", [("mixed_mfma16", 1e-6, 1e-5), ("mixed_mfma32", 1e-6, 1e-5)])
+# BF16 hi+lo carries 16 significant bits of each jamp (2^-16 = 1.5e-5 at
+# most, a few 1e-6 typically); FP16 hi+lo about 22 and FP32 operands 24
+@pytest.mark.parametrize("variant,med,mx", [("mixed_mfma16", 1e-6, 1e-5), ("mixed_mfma32", 1e-6, 1e-5),
+                                            ("mixed_mfma_bf16", 1e-5, 1e-3)])
 @pytest.mark.parametrize("proc", ["ggttg", "ggttgg"])
 def test_mfma_colour_sum_matches_valu(B, dev, proc, variant, med, mx):
-    """The MFMA colour sums (FP16 hi+lo jamps or FP32 operands, FP32
+    """The MFMA colour sums (FP16 or BF16 hi+lo jamps or FP32 operands, FP32
     accumulation) agree with the FP32 vector-ALU colour sum of the same FP32
     jamps, including a batch with a ragged last wave."""
     mom = config_events(proc, 2048 + 29)

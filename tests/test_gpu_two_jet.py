@@ -59,7 +59,7 @@ def test_fp64_matches_oracle(oracle_lib, dev, proc):
                proc)
 
 
-@pytest.mark.parametrize("precision", ["mixed", "mixed_mfma16"])
+@pytest.mark.parametrize("precision", ["mixed", "mixed_mfma16", "mixed_mfma_bf16"])
 @pytest.mark.parametrize("proc", TWO_JET)
 def test_mixed_matches_oracle(oracle_lib, dev, proc, precision):
     mom = config_events(proc, NCHECK)
