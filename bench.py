@@ -61,7 +61,7 @@ def kernel_digest(variant):
     fns = {"valu": ("static T colour_sum", "static void den_fill_f32"),
            "mfma_f16_hilo": ("static void den_fill_f32",),
            "mfma_bf16_hilo": ("static void den_fill_f32",),
-           "fp64": ("static T colour_sum", "static void lc_fill")}[variant]
+           "fp64": ("static T colour_sum", "static void den_fill_f64")}[variant]
     for fn in fns:
         h.update(_function(inc, fn).encode())
     # the kernel template itself (not the rest of kernels.hpp: dispatch code
@@ -70,7 +70,7 @@ def kernel_digest(variant):
         kh = fh.read()
     names = {"valu": ("void me_kernel_kc(",), "mfma_f16_hilo": ("void me_mfma_body(", "void me_kernel_mfma("),
              "mfma_bf16_hilo": ("void me_mfma_body(", "void me_kernel_mfma_bf16("),
-             "fp64": ("void me_kernel_ldsjamp(",)}[variant]
+             "fp64": ("void me_kernel_ldsjamp_kc(",)}[variant]
     for name in names:
         a = kh.rindex("template", 0, kh.index(name))
         h.update(kh[a:kh.index("\n}\n", a)].encode())
@@ -256,7 +256,7 @@ def main():
         "roofline_fp64": {"bound": "alu", "achieved": ach64 / 1e12, "peak": FP64_VECTOR_PEAK / 1e12,
                           "unit": "TFLOP/s", "frac": ach64 / FP64_VECTOR_PEAK, "traffic": measured_traffic("fp64"),
                           "algorithmic_bytes": n * info["bytes_per_event"],
-                          "kernel": "me_kernel_ldsjamp<Proc_ggttgg, double>", "kernel_ms": t_launch64 * 1e3},
+                          "kernel": "me_kernel_ldsjamp_kc<Proc_ggttgg, 2>", "kernel_ms": t_launch64 * 1e3},
     }
 
     # gg -> t tbar ggg (1240 diagrams, 120 colour flows), split form: part

@@ -861,7 +861,8 @@ def all_programs(budget=None):
         p.f32_lds_jamps = p.name in F32_LDS_JAMPS
         p.mixed_mfma = p.name in MIXED_MFMA
         p.den_cache_f32 = p.name in DEN_CACHE_F32
-        p.den_cache_f64 = p.name in DEN_CACHE_F64 and not p.fp64_lds_jamps
+        p.den_cache_f64 = p.name in DEN_CACHE_F64
+        p.fp64_kc_waves = FP64_KC_WAVES.get(p.name, 1)
         b64, i64 = DEFAULT_SCHEDULE_F64.get(p.name, (256, 4))
         b32, i32 = DEFAULT_SCHEDULE_F32.get(p.name, (512, 4))
         schedule(p, budget if budget is not None else b32, i32)
@@ -874,7 +875,7 @@ def all_programs(budget=None):
 # (budget in FP64 dwords, greedy passes) per process and arithmetic type,
 # and whether amplitudes share half contractions; chosen by measurement on
 # gfx950 (2^20 gg -> t tbar gg events)
-DEFAULT_SCHEDULE_F64 = {"eemumu": (256, 4), "ggtt": (256, 4), "ggttg": (256, 4), "ggttgg": (320, 4)}
+DEFAULT_SCHEDULE_F64 = {"eemumu": (256, 4), "ggtt": (256, 4), "ggttg": (256, 4), "ggttgg": (240, 4)}
 DEFAULT_SCHEDULE_F32 = {"eemumu": (256, 4), "ggtt": (256, 4), "ggttg": (384, 1), "ggttgg": (448, 2)}
 SHARE_HALF = {"ggttg": False, "ggttgg": False, "ggttggg": True}
 # FP64 forms that keep their jamps in LDS (frees 4 registers per colour flow
@@ -882,13 +883,17 @@ SHARE_HALF = {"ggttg": False, "ggttgg": False, "ggttggg": True}
 FP64_LDS_JAMPS = {"ggttgg"}
 # the same for the mixed form's vector-ALU kernel
 F32_LDS_JAMPS = set()
+# waves per block that share one event's kinematic cache in the FP64 form
+# with jamps in LDS
+FP64_KC_WAVES = {"ggttgg": 2}
 # mixed forms whose vector-ALU kernel forms the propagator factors once per
 # event into LDS instead of once per helicity
 DEN_CACHE_F32 = {"eemumu", "ggtt", "ggttg", "ggttgg", "uutt", "uxutt", "uuttg", "uxuttg", "ugttu", "guttu",
                  "uxgttux", "guxttux", "uuttgg", "uxuttgg", "ugttug", "guttug", "uxgttuxg", "guxttuxg", "ggttuux",
                  "uuttuux", "uuttddx", "uuttuu", "udttud", "uxuxttuxux"}
-# the same for FP64 forms whose jamps stay in registers
-DEN_CACHE_F64 = {"eemumu", "ggtt", "ggttg", "uutt", "uxutt", "uuttg", "uxuttg", "ugttu", "guttu", "uxgttux",
+# the same for the FP64 forms (with jamps in LDS: the helicities of an event
+# are spread over FP64_KC_WAVES waves that share one cache)
+DEN_CACHE_F64 = {"ggttgg", "eemumu", "ggtt", "ggttg", "uutt", "uxutt", "uuttg", "uxuttg", "ugttu", "guttu", "uxgttux",
                  "guxttux", "uuttgg", "uxuttgg", "ugttug", "guttug", "uxgttuxg", "guxttuxg", "ggttuux",
                  "uuttuux", "uuttddx", "uuttuu", "udttud", "uxuxttuxux"}
 # processes whose default mixed form (ME_MIXED) sums colours on FP16 hi+lo
