@@ -36,9 +36,10 @@ FP64_VECTOR_PEAK = 78.6e12    # MI355X fp64 vector FLOP/s
 # otherwise.
 PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 MEASURED_TRAFFIC = {
-    "valu": {"digest": "73e9a19e921d018c", "fetch_kib": 99030, "write_kib": 8192},
-    "mfma_f16_hilo": {"digest": "056195a2b18fbafb", "fetch_kib": 99035, "write_kib": 8192},
-    "fp64": {"digest": "2b07ee9521cf45e3", "fetch_kib": 8752198, "write_kib": 34080111},
+    "valu": {"digest": "0ef09884c3e4225b", "fetch_kib": 99030, "write_kib": 8192},
+    "mfma_f16_hilo": {"digest": "7475b8ae07de03f0", "fetch_kib": 99044, "write_kib": 8192},
+    "mfma_bf16_hilo": {"digest": "55199d4cbc46879d", "fetch_kib": 99044, "write_kib": 8192},
+    "fp64": {"digest": "271db46bab37b7a9", "fetch_kib": 99690, "write_kib": 8192},
 }
 
 
