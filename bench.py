@@ -69,7 +69,7 @@ def kernel_digest(variant):
     # does not change the kernel's binary)
     with open(os.path.join(csrc, "kernels.hpp")) as fh:
         kh = fh.read()
-    names = {"valu": ("void me_kernel_kc(",), "mfma_f16_hilo": ("void me_mfma_body(", "void me_kernel_mfma("),
+    names = {"valu": ("void me_kernel_kcw(",), "mfma_f16_hilo": ("void me_mfma_body(", "void me_kernel_mfma("),
              "mfma_bf16_hilo": ("void me_mfma_body(", "void me_kernel_mfma_bf16("),
              "fp64": ("void me_kernel_ldsjamp_kc(",)}[variant]
     for name in names:
@@ -197,7 +197,7 @@ def main():
     r64 = out64.cpu().numpy()
     forms = {"mfma_f16_hilo": (me_mfma, "me_kernel_mfma<Proc_ggttgg, false>"),
              "mfma_bf16_hilo": (me_bf16, "me_kernel_mfma_bf16<Proc_ggttgg>"),
-             "valu": (me_valu, "me_kernel_kc<Proc_ggttgg, float>")}
+             "valu": (me_valu, "me_kernel_kcw<Proc_ggttgg, 2>")}
     variants, timed = {}, {}
     for form, (mef, kname) in forms.items():
         o = torch.empty(args.nevt, dtype=torch.float64, device=dev)

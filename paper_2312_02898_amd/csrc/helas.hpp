@@ -487,6 +487,7 @@ template <class J> __device__ __forceinline__ void hold_jamp(J&, int) {}
 // forms them in place from the momenta otherwise (this type).
 struct NoKinCache {
   static constexpr bool kCached = false;
+  static constexpr bool kMom = false;
   static constexpr bool kLc = false;   // no light-cone cache either
   __device__ __forceinline__ double lcs(int) const { return 0.0; }
   __device__ __forceinline__ double pair(int) const { return 0.0; }

@@ -63,9 +63,14 @@ __global__ __launch_bounds__(256) void me_kernel(const double* __restrict__ mom,
 // slots.  The per-iteration offset passes through an empty asm statement, so
 // the reads stay inside the helicity loop where the schedule put them instead
 // of being hoisted out of it and held in registers across the loop.
-template <class T, int S = 256>
+// With M, the cache also holds the schedule's momentum sums (one 16-byte
+// entry per slot) and both helicity states of each external spinor (two
+// 16-byte halves per state, in separate planes), for the FP32 form: the
+// helicity program then reads no momenta at all.
+template <class T, int S = 256, bool M = false>
 struct LdsKinCache {
   static constexpr bool kCached = true;
+  static constexpr bool kMom = M;
   static constexpr bool kLc = false;   // cached factors already hold the light-cone forms
   __device__ __forceinline__ double lcs(int) const { return 0.0; }
   __device__ __forceinline__ double pair(int) const { return 0.0; }
@@ -101,6 +106,43 @@ struct LdsKinCache {
   }
   __device__ __forceinline__ void set_r(int s, T v) { re[s * S + off] = v; }
   __device__ __forceinline__ void set_c(int s, cx<T> v) { cxs[s * S + off] = v; }
+  // momentum sums and spinors (M only; FP32): slot s of event t at
+  // km[s * S + t]; state lam of spinor slot j in halves at
+  // ksp[((2 (2j + (lam > 0)) + half) * S + t]
+  float4* km = nullptr;
+  float4* ksp = nullptr;
+  __device__ __forceinline__ mom<T> k_at(int s, int o) const {
+    const float4 v = km[s * S + o];
+    return mom<T>{{v.x, v.y, v.z, v.w}};
+  }
+  __device__ __forceinline__ mom<T> k(int s) const { return k_at(s, off); }
+  __device__ __forceinline__ mom<T> k_opq(int s) const {
+    int o = off;
+    asm volatile("" : "+v"(o));
+    return k_at(s, o);
+  }
+  __device__ __forceinline__ wf<T> sp_at(int j, int lam, int o) const {
+    const int b = 2 * (2 * j + (lam > 0 ? 1 : 0));
+    const float4 a = ksp[b * S + o], c = ksp[(b + 1) * S + o];
+    wf<T> w;
+    w.c[0] = cx<T>{a.x, a.y}; w.c[1] = cx<T>{a.z, a.w};
+    w.c[2] = cx<T>{c.x, c.y}; w.c[3] = cx<T>{c.z, c.w};
+    return w;
+  }
+  __device__ __forceinline__ wf<T> sp(int j, int lam) const { return sp_at(j, lam, off); }
+  __device__ __forceinline__ wf<T> sp_opq(int j, int lam) const {
+    int o = off;
+    asm volatile("" : "+v"(o));
+    return sp_at(j, lam, o);
+  }
+  __device__ __forceinline__ void set_k(int s, const mom<T>& v) {
+    km[s * S + off] = float4{float(v.k[0]), float(v.k[1]), float(v.k[2]), float(v.k[3])};
+  }
+  __device__ __forceinline__ void set_sp(int j, int lam, const wf<T>& w) {
+    const int b = 2 * (2 * j + (lam > 0 ? 1 : 0));
+    ksp[b * S + off] = float4{float(w.c[0].r), float(w.c[0].i), float(w.c[1].r), float(w.c[1].i)};
+    ksp[(b + 1) * S + off] = float4{float(w.c[2].r), float(w.c[2].i), float(w.c[3].r), float(w.c[3].i)};
+  }
 };
 
 // The kinematic cache in LDS with the vector-ALU colour sum (256-thread
@@ -144,6 +186,54 @@ __global__ __launch_bounds__(256) void me_kernel_kc(const double* __restrict__ m
   if (out) store_me(prm, out, e, acc * (P::coupling_factor(prm) / (P::CDEN * P::IDEN)));
 }
 
+// Mixed form with the vector-ALU colour sum and the full kinematic cache
+// (propagator factors, polarisation bases, momentum sums and both helicity
+// states of the external spinors, in FP32): a block of W waves evaluates 64
+// events, wave w the helicities w, w + W, ... of each, so one per-event cache,
+// formed by wave 0 before the helicity loop, serves W lanes.  The helicity
+// program reads no momenta, so none stay in registers across the loop.  Each
+// wave's helicity partial sums meet in LDS and wave 0 adds them in wave
+// order.  Lanes past the end of the batch evaluate the last event again
+// (every wave reaches both barriers) and store nothing.
+template <class P, int W>
+__global__ __launch_bounds__(64 * W) void me_kernel_kcw(const double* __restrict__ mom, int64_t nevt,
+                                                         double* __restrict__ out, const MeParams prm) {
+  constexpr int KR = P::KC_RE_F32, KC = P::KC_CX_F32, KE = P::KC_EPS_F32;
+  constexpr int KM = P::KC_MOM_F32, KS = P::KC_SP_F32;
+  __shared__ float kre[(KR > 0 ? KR : 1) * 64];
+  __shared__ cx<float> kcx[(KC > 0 ? KC : 1) * 64];
+  __shared__ float keps[5 * (KE > 0 ? KE : 1) * 64];
+  __shared__ float4 kmo[(KM > 0 ? KM : 1) * 64];
+  __shared__ float4 ksp[4 * (KS > 0 ? KS : 1) * 64];
+  __shared__ double part[W * 64];
+  const int lane = threadIdx.x % 64;
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / 64);
+  const int64_t e = int64_t(blockIdx.x) * 64 + lane;
+  const bool live = e < nevt;
+  const int64_t ec = live ? e : nevt - 1;
+  LdsKinCache<float, 64, true> dc{kre, kcx, keps, lane, kmo, ksp};
+  double p[P::NPAR][4];
+  load_on_shell<P::MASSIVE>(mom + ec * (4 * P::NPAR), p, prm.mt);
+  if (wave == 0) P::template den_fill_f32<float>(p, prm, dc);
+  __syncthreads();
+  double acc = 0.0;
+  for (int ih = wave; ih < prm.nhel; ih += W) {
+    asm volatile("" : "+v"(dc.off));
+    const unsigned hel = prm.hel[ih];
+    cx<float> jamp[P::NCOLOR];
+    P::template amplitudes<float>(p, hel, prm, jamp, dc);
+    acc += double(P::template colour_sum<float>(jamp));
+  }
+  part[wave * 64 + lane] = acc;
+  __syncthreads();
+  if (wave == 0 && live && out) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) s += part[w * 64 + lane];
+    store_me(prm, out, e, s * (P::coupling_factor(prm) / (P::CDEN * P::IDEN)));
+  }
+}
+
 // Per-event light-cone cache of the FP64 form in LDS (128-thread blocks):
 // the small light-cone component of each outgoing leg and the invariants of
 // the pairs of massless outgoing legs, formed once per event and read where
@@ -152,6 +242,7 @@ __global__ __launch_bounds__(256) void me_kernel_kc(const double* __restrict__ m
 // reads stay inside the helicity loop instead of being held in registers.
 struct LdsLcCache {
   static constexpr bool kCached = false;
+  static constexpr bool kMom = false;
   static constexpr bool kLc = true;
   double* base;
   int npair0;   // first pair slot (after the legs)
@@ -387,6 +478,11 @@ int launch(int mode, const double* mom, int64_t nevt, double* out, double* out_h
       const int64_t nb = (nevt + 127) / 128;
       hipLaunchKernelGGL((me_kernel_ldsjamp<P, float>), dim3(unsigned(nb)), dim3(128), 0, stream, mom, nevt,
                          out, nullptr, prm);
+    } else if constexpr (P::KC_MOM_F32 > 0) {
+      const int64_t nb = (nevt + 63) / 64;
+      if (nb > 0x7fffffffLL) return -1;
+      constexpr int W = P::F32_KC_WAVES;
+      hipLaunchKernelGGL((me_kernel_kcw<P, W>), dim3(unsigned(nb)), dim3(64 * W), 0, stream, mom, nevt, out, prm);
     } else if constexpr (P::KC_RE_F32 + P::KC_CX_F32 + P::KC_EPS_F32 > 0) {
       hipLaunchKernelGGL((me_kernel_kc<P, float>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
                          nullptr, prm);

@@ -863,6 +863,8 @@ def all_programs(budget=None):
         p.den_cache_f32 = p.name in DEN_CACHE_F32
         p.den_cache_f64 = p.name in DEN_CACHE_F64
         p.fp64_kc_waves = FP64_KC_WAVES.get(p.name, 1)
+        p.mom_cache_f32 = p.name in MOM_CACHE_F32 and p.den_cache_f32
+        p.f32_kc_waves = F32_KC_WAVES.get(p.name, 1)
         b64, i64 = DEFAULT_SCHEDULE_F64.get(p.name, (256, 4))
         b32, i32 = DEFAULT_SCHEDULE_F32.get(p.name, (512, 4))
         schedule(p, budget if budget is not None else b32, i32)
@@ -886,6 +888,11 @@ F32_LDS_JAMPS = set()
 # waves per block that share one event's kinematic cache in the FP64 form
 # with jamps in LDS
 FP64_KC_WAVES = {"ggttgg": 2}
+# mixed forms whose vector-ALU kernel also caches the momentum sums and both
+# helicity states of the external spinors per event (their helicities spread
+# over F32_KC_WAVES waves that share the cache)
+MOM_CACHE_F32 = {"ggttgg"}
+F32_KC_WAVES = {"ggttgg": 2}
 # mixed forms whose vector-ALU kernel forms the propagator factors once per
 # event into LDS instead of once per helicity
 DEN_CACHE_F32 = {"eemumu", "ggtt", "ggttg", "ggttgg", "uutt", "uxutt", "uuttg", "uxuttg", "ugttu", "guttu",

@@ -70,6 +70,7 @@ template <int J, class Q = P> void parts(const double (&p)[P::NPAR][4], unsigned
 // stands in for the FP64 kernel's per-event light-cone cache
 struct HostLcCache {
   static constexpr bool kCached = false;
+  static constexpr bool kMom = false;
   static constexpr bool kLc = true;
   double v[64];
   int npair0;
@@ -80,7 +81,16 @@ struct HostLcCache {
 };
 template <class T> struct HostKinCache {
   static constexpr bool kCached = true;
+  static constexpr bool kMom = true;   // momentum sums and spinors too, where the form caches them
   static constexpr bool kLc = false;
+  mom<T> km[64];
+  wf<T> sps[16][2];
+  mom<T> k(int s) const { return km[s]; }
+  mom<T> k_opq(int s) const { return km[s]; }
+  wf<T> sp(int j, int lam) const { return sps[j][lam > 0]; }
+  wf<T> sp_opq(int j, int lam) const { return sp(j, lam); }
+  void set_k(int s, const mom<T>& v) { km[s] = v; }
+  void set_sp(int j, int lam, const wf<T>& w) { sps[j][lam > 0] = w; }
   double lcs(int) const { return 0.0; }
   double pair(int) const { return 0.0; }
   T re[64];
@@ -120,8 +130,11 @@ void jamps(const double (&p)[Q::NPAR][4], unsigned h, const MeParams& prm, cx<T>
     Q::template amplitudes_f64<T>(p, h, prm, J);
   } else if constexpr (Q::KC_RE_F32 + Q::KC_CX_F32 + Q::KC_EPS_F32 > 0) {
     static_assert(Q::KC_RE_F32 <= 64 && Q::KC_CX_F32 <= 64 && Q::KC_EPS_F32 <= 16, "host cache too small");
+    static_assert(Q::KC_MOM_F32 <= 64 && Q::KC_SP_F32 <= 16, "host cache too small");
     HostKinCache<T> dc;
     for (int s = 0; s < 64; ++s) { dc.re[s] = T(1e30); dc.cxs[s] = cx<T>{T(1e30), T(1e30)}; }
+    for (int s = 0; s < 64; ++s) for (int c = 0; c < 4; ++c) dc.km[s].k[c] = T(1e30);
+    for (int s = 0; s < 16; ++s) for (int l = 0; l < 2; ++l) for (int c = 0; c < 4; ++c) dc.sps[s][l].c[c] = cx<T>{T(1e30), T(1e30)};
     for (int s = 0; s < 16; ++s) for (int c = 0; c < 5; ++c) dc.eb[s][c] = T(1e30);
     Q::template den_fill_f32<T>(p, prm, dc);
     Q::template amplitudes_f32<T>(p, h, prm, J, dc);
