@@ -478,7 +478,7 @@ int launch(int mode, const double* mom, int64_t nevt, double* out, double* out_h
       const int64_t nb = (nevt + 127) / 128;
       hipLaunchKernelGGL((me_kernel_ldsjamp<P, float>), dim3(unsigned(nb)), dim3(128), 0, stream, mom, nevt,
                          out, nullptr, prm);
-    } else if constexpr (P::KC_MOM_F32 > 0) {
+    } else if constexpr (P::KC_MOM_F32 + P::KC_SP_F32 > 0) {
       const int64_t nb = (nevt + 63) / 64;
       if (nb > 0x7fffffffLL) return -1;
       constexpr int W = P::F32_KC_WAVES;

@@ -864,7 +864,7 @@ def all_programs(budget=None):
         p.den_cache_f64 = p.name in DEN_CACHE_F64
         p.fp64_kc_waves = FP64_KC_WAVES.get(p.name, 1)
         p.mom_cache_f32 = p.name in MOM_CACHE_F32 and p.den_cache_f32
-        p.f32_kc_waves = F32_KC_WAVES.get(p.name, 1)
+        p.f32_kc_waves = F32_KC_WAVES if p.mom_cache_f32 else 1
         b64, i64 = DEFAULT_SCHEDULE_F64.get(p.name, (256, 4))
         b32, i32 = DEFAULT_SCHEDULE_F32.get(p.name, (512, 4))
         schedule(p, budget if budget is not None else b32, i32)
@@ -888,11 +888,6 @@ F32_LDS_JAMPS = set()
 # waves per block that share one event's kinematic cache in the FP64 form
 # with jamps in LDS
 FP64_KC_WAVES = {"ggttgg": 2}
-# mixed forms whose vector-ALU kernel also caches the momentum sums and both
-# helicity states of the external spinors per event (their helicities spread
-# over F32_KC_WAVES waves that share the cache)
-MOM_CACHE_F32 = {"ggttgg"}
-F32_KC_WAVES = {"ggttgg": 2}
 # mixed forms whose vector-ALU kernel forms the propagator factors once per
 # event into LDS instead of once per helicity
 DEN_CACHE_F32 = {"eemumu", "ggtt", "ggttg", "ggttgg", "uutt", "uxutt", "uuttg", "uxuttg", "ugttu", "guttu",
@@ -903,6 +898,12 @@ DEN_CACHE_F32 = {"eemumu", "ggtt", "ggttg", "ggttgg", "uutt", "uxutt", "uuttg", 
 DEN_CACHE_F64 = {"ggttgg", "eemumu", "ggtt", "ggttg", "uutt", "uxutt", "uuttg", "uxuttg", "ugttu", "guttu", "uxgttux",
                  "guxttux", "uuttgg", "uxuttgg", "ugttug", "guttug", "uxgttuxg", "guxttuxg", "ggttuux",
                  "uuttuux", "uuttddx", "uuttuu", "udttud", "uxuxttuxux"}
+# mixed forms whose vector-ALU kernel also caches the momentum sums and both
+# helicity states of the external spinors per event (their helicities spread
+# over F32_KC_WAVES waves that share the cache); measured faster for all but
+# the q g > t t~ q g channels and g g > t t~ u u~, where it made no gain
+MOM_CACHE_F32 = DEN_CACHE_F32 - {"ugttug", "guttug", "uxgttuxg", "guxttuxg", "ggttuux"}
+F32_KC_WAVES = 2
 # processes whose default mixed form (ME_MIXED) sums colours on FP16 hi+lo
 # MFMA; the others use the vector ALU (chosen by measurement)
 MIXED_MFMA = set()

@@ -42,4 +42,5 @@ def test_shipped_schedule_parameters():
     assert program.SHARE_HALF == {"ggttg": False, "ggttgg": False, "ggttggg": True}
     assert program.FP64_LDS_JAMPS == {"ggttgg"} and program.FP64_KC_WAVES == {"ggttgg": 2}
     assert "ggttgg" in program.DEN_CACHE_F64
-    assert program.MOM_CACHE_F32 == {"ggttgg"} and program.F32_KC_WAVES == {"ggttgg": 2}
+    assert program.MOM_CACHE_F32 == program.DEN_CACHE_F32 - {"ugttug", "guttug", "uxgttuxg", "guxttuxg", "ggttuux"}
+    assert program.F32_KC_WAVES == 2
