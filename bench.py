@@ -69,8 +69,8 @@ def kernel_digest(variant):
     # does not change the kernel's binary)
     with open(os.path.join(csrc, "kernels.hpp")) as fh:
         kh = fh.read()
-    names = {"valu": ("void me_kernel_kcw(",), "mfma_f16_hilo": ("void me_mfma_body(", "void me_kernel_mfma("),
-             "mfma_bf16_hilo": ("void me_mfma_body(", "void me_kernel_mfma_bf16("),
+    names = {"valu": ("void me_kernel_kcw(",), "mfma_f16_hilo": ("void me_mfma_body_w(", "void me_kernel_mfma("),
+             "mfma_bf16_hilo": ("void me_mfma_body_w(", "void me_kernel_mfma_bf16("),
              "fp64": ("void me_kernel_ldsjamp_kc(",)}[variant]
     for name in names:
         a = kh.rindex("template", 0, kh.index(name))

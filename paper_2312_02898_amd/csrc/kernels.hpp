@@ -411,18 +411,86 @@ __device__ __forceinline__ void me_mfma_body(const double* __restrict__ mom, int
   if (e < nevt) store_me(prm, out, e, acc * (P::coupling_factor(prm) / (P::CDEN * P::IDEN)));
 }
 
+// The same with the full kinematic cache of me_kernel_kcw (momentum sums and
+// spinors too): four waves share one block's 64 events, wave w evaluating
+// the helicities w, w + 4, ...; each wave sums the colours of its 64 events
+// for its helicity on MFMA as above, and the waves' helicity partial sums
+// meet in LDS (wave order).  Every lane of every wave stays active.
+template <class P, int OPS>
+__device__ __forceinline__ void me_mfma_body_w(const double* __restrict__ mom, int64_t nevt,
+                                               double* __restrict__ out, const MeParams& prm) {
+  constexpr int W = 4;
+  constexpr int kLds = OPS == kMfmaF32 ? kColourLds32Bytes : ColourTile<P::NCOLOR>::kLdsBytes;
+  __shared__ __attribute__((aligned(16))) char lds_all[W * kLds];
+  constexpr int KR = P::KC_RE_F32, KC = P::KC_CX_F32, KE = P::KC_EPS_F32;
+  constexpr int KM = P::KC_MOM_F32, KS = P::KC_SP_F32;
+  __shared__ float kre[(KR > 0 ? KR : 1) * 64];
+  __shared__ cx<float> kcx[(KC > 0 ? KC : 1) * 64];
+  __shared__ float keps[5 * (KE > 0 ? KE : 1) * 64];
+  __shared__ float4 kmo[(KM > 0 ? KM : 1) * 64];
+  __shared__ float4 ksp[4 * (KS > 0 ? KS : 1) * 64];
+  __shared__ double part[W * 64];
+  const int lane = threadIdx.x % 64;
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / 64);
+  const int64_t e = int64_t(blockIdx.x) * 64 + lane;
+  const bool live = e < nevt;
+  const int64_t ec = live ? e : nevt - 1;
+  void* lds = lds_all + wave * kLds;
+  const ColourA<P::NCOLOR> A = colour_a<P::NCOLOR>(P::cmat(), lane);
+  const ColourA32<P::NCOLOR> A32 = colour_a32<P::NCOLOR>(P::cmat(), lane);
+  const ColourA<P::NCOLOR, __bf16> Ab = colour_a<P::NCOLOR, __bf16>(P::cmat(), lane);
+  LdsKinCache<float, 64, true> dc{kre, kcx, keps, lane, kmo, ksp};
+  double p[P::NPAR][4];
+  load_on_shell<P::MASSIVE>(mom + ec * (4 * P::NPAR), p, prm.mt);
+  if (wave == 0) P::template den_fill_f32<float>(p, prm, dc);
+  __syncthreads();
+  double acc = 0.0;
+  for (int ih = wave; ih < prm.nhel; ih += W) {
+    asm volatile("" : "+v"(dc.off));
+    const unsigned hel = prm.hel[ih];
+    cx<float> jamp[P::NCOLOR];
+    P::template amplitudes<float>(p, hel, prm, jamp, dc);
+    if constexpr (OPS == kMfmaF32)
+      acc += double(colour_sum_mfma32<P::NCOLOR>(jamp, A32, lds, lane));
+    else if constexpr (OPS == kMfmaBf16HiLo)
+      acc += double(colour_sum_mfma<P::NCOLOR, __bf16>(jamp, Ab, lds, lane));
+    else
+      acc += double(colour_sum_mfma<P::NCOLOR>(jamp, A, lds, lane));
+  }
+  part[wave * 64 + lane] = acc;
+  __syncthreads();
+  if (wave == 0 && live && out) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) s += part[w * 64 + lane];
+    store_me(prm, out, e, s * (P::coupling_factor(prm) / (P::CDEN * P::IDEN)));
+  }
+}
+
+// events per 256-lane block of the MFMA kernels
+template <class P>
+constexpr int mfma_block_events() {
+  return P::KC_MOM_F32 + P::KC_SP_F32 > 0 ? 64 : 256;
+}
+
 // FP16 hi+lo (F32OPS false) or FP32 (true) colour-sum operands
 template <class P, bool F32OPS>
 __global__ __launch_bounds__(256) void me_kernel_mfma(const double* __restrict__ mom, int64_t nevt,
                                                       double* __restrict__ out, const MeParams prm) {
-  me_mfma_body<P, F32OPS ? kMfmaF32 : kMfmaF16HiLo>(mom, nevt, out, prm);
+  if constexpr (mfma_block_events<P>() == 64)
+    me_mfma_body_w<P, F32OPS ? kMfmaF32 : kMfmaF16HiLo>(mom, nevt, out, prm);
+  else
+    me_mfma_body<P, F32OPS ? kMfmaF32 : kMfmaF16HiLo>(mom, nevt, out, prm);
 }
 
 // BF16 hi+lo colour-sum operands
 template <class P>
 __global__ __launch_bounds__(256) void me_kernel_mfma_bf16(const double* __restrict__ mom, int64_t nevt,
                                                            double* __restrict__ out, const MeParams prm) {
-  me_mfma_body<P, kMfmaBf16HiLo>(mom, nevt, out, prm);
+  if constexpr (mfma_block_events<P>() == 64)
+    me_mfma_body_w<P, kMfmaBf16HiLo>(mom, nevt, out, prm);
+  else
+    me_mfma_body<P, kMfmaBf16HiLo>(mom, nevt, out, prm);
 }
 
 // mode: ME_MODE_FP64; ME_MODE_MIXED (colour sum on the unit chosen for the
@@ -462,14 +530,17 @@ int launch(int mode, const double* mom, int64_t nevt, double* out, double* out_h
               mode == ME_MODE_MIXED_MFMA32 || mode == ME_MODE_MIXED_MFMABF16) && P::NCOLOR >= 6 &&
              P::NCOLOR <= 32) {
     if (out_hel || !out) return -1;
+    constexpr int EB = mfma_block_events<P>();
+    const int64_t nbm = (nevt + EB - 1) / EB;
+    if (nbm > 0x7fffffffLL) return -1;
     if (mode == ME_MODE_MIXED_MFMA32)
-      hipLaunchKernelGGL((me_kernel_mfma<P, true>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
+      hipLaunchKernelGGL((me_kernel_mfma<P, true>), dim3(unsigned(nbm)), dim3(block), 0, stream, mom, nevt, out,
                          prm);
     else if (mode == ME_MODE_MIXED_MFMABF16)
-      hipLaunchKernelGGL((me_kernel_mfma_bf16<P>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
+      hipLaunchKernelGGL((me_kernel_mfma_bf16<P>), dim3(unsigned(nbm)), dim3(block), 0, stream, mom, nevt, out,
                          prm);
     else
-      hipLaunchKernelGGL((me_kernel_mfma<P, false>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
+      hipLaunchKernelGGL((me_kernel_mfma<P, false>), dim3(unsigned(nbm)), dim3(block), 0, stream, mom, nevt, out,
                          prm);
   } else if (mode == ME_MODE_MIXED || mode == ME_MODE_MIXED_VALU || mode == ME_MODE_MIXED_MFMA32 ||
              mode == ME_MODE_MIXED_MFMA16 || mode == ME_MODE_MIXED_MFMABF16) {
