@@ -905,8 +905,9 @@ DEN_CACHE_F64 = {"ggttgg", "eemumu", "ggtt", "ggttg", "uutt", "uxutt", "uuttg", 
 MOM_CACHE_F32 = DEN_CACHE_F32 - {"ugttug", "guttug", "uxgttuxg", "guxttuxg", "ggttuux"}
 F32_KC_WAVES = 2
 # processes whose default mixed form (ME_MIXED) sums colours on FP16 hi+lo
-# MFMA; the others use the vector ALU (chosen by measurement)
-MIXED_MFMA = set()
+# MFMA; the others use the vector ALU (chosen by measurement on 2^20 events
+# of each process's configuration)
+MIXED_MFMA = {"uuttgg", "uxuttgg", "uuttuu", "uuttuux", "uxuxttuxux"}
 
 # Split form (jamps in a workspace, amplitudes in several kernels) for the
 # processes whose colour flows do not fit in registers: per arithmetic type
