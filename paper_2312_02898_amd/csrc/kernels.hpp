@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "colour_mfma.hpp"
 #include "epilogue.hpp"
 #include "helas.hpp"
@@ -106,14 +108,27 @@ struct LdsKinCache {
   }
   __device__ __forceinline__ void set_r(int s, T v) { re[s * S + off] = v; }
   __device__ __forceinline__ void set_c(int s, cx<T> v) { cxs[s * S + off] = v; }
-  // momentum sums and spinors (M only; FP32): slot s of event t at
-  // km[s * S + t]; state lam of spinor slot j in halves at
-  // ksp[((2 (2j + (lam > 0)) + half) * S + t]
-  float4* km = nullptr;
-  float4* ksp = nullptr;
+  // momentum sums and spinors (M only), in 16-byte chunks (float4 for
+  // FP32, double2 for FP64: NV chunks per momentum, 2 NV per spinor state):
+  // chunk h of slot s of event t at km[(s NV + h) S + t]; chunk h of state
+  // lam of spinor slot j at ksp[((2j + (lam > 0)) 2 NV + h) S + t]
+  using V = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+  static constexpr int NV = sizeof(T) / 4;
+  V* km = nullptr;
+  V* ksp = nullptr;
+  __device__ __forceinline__ static void unpack(const V& v, T* x) {
+    if constexpr (sizeof(T) == 8) { x[0] = v.x; x[1] = v.y; }
+    else { x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w; }
+  }
+  __device__ __forceinline__ static V pack(const T* x) {
+    if constexpr (sizeof(T) == 8) return V{x[0], x[1]};
+    else return V{x[0], x[1], x[2], x[3]};
+  }
   __device__ __forceinline__ mom<T> k_at(int s, int o) const {
-    const float4 v = km[s * S + o];
-    return mom<T>{{v.x, v.y, v.z, v.w}};
+    mom<T> K;
+#pragma unroll
+    for (int h = 0; h < NV; ++h) unpack(km[(s * NV + h) * S + o], K.k + h * (4 / NV));
+    return K;
   }
   __device__ __forceinline__ mom<T> k(int s) const { return k_at(s, off); }
   __device__ __forceinline__ mom<T> k_opq(int s) const {
@@ -122,11 +137,13 @@ struct LdsKinCache {
     return k_at(s, o);
   }
   __device__ __forceinline__ wf<T> sp_at(int j, int lam, int o) const {
-    const int b = 2 * (2 * j + (lam > 0 ? 1 : 0));
-    const float4 a = ksp[b * S + o], c = ksp[(b + 1) * S + o];
+    const int b = (2 * j + (lam > 0 ? 1 : 0)) * 2 * NV;
+    T x[8];
+#pragma unroll
+    for (int h = 0; h < 2 * NV; ++h) unpack(ksp[(b + h) * S + o], x + h * (4 / NV));
     wf<T> w;
-    w.c[0] = cx<T>{a.x, a.y}; w.c[1] = cx<T>{a.z, a.w};
-    w.c[2] = cx<T>{c.x, c.y}; w.c[3] = cx<T>{c.z, c.w};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) w.c[c] = cx<T>{x[2 * c], x[2 * c + 1]};
     return w;
   }
   __device__ __forceinline__ wf<T> sp(int j, int lam) const { return sp_at(j, lam, off); }
@@ -135,13 +152,17 @@ struct LdsKinCache {
     asm volatile("" : "+v"(o));
     return sp_at(j, lam, o);
   }
-  __device__ __forceinline__ void set_k(int s, const mom<T>& v) {
-    km[s * S + off] = float4{float(v.k[0]), float(v.k[1]), float(v.k[2]), float(v.k[3])};
+  __device__ __forceinline__ void set_k(int s, const mom<T>& K) {
+#pragma unroll
+    for (int h = 0; h < NV; ++h) km[(s * NV + h) * S + off] = pack(K.k + h * (4 / NV));
   }
   __device__ __forceinline__ void set_sp(int j, int lam, const wf<T>& w) {
-    const int b = 2 * (2 * j + (lam > 0 ? 1 : 0));
-    ksp[b * S + off] = float4{float(w.c[0].r), float(w.c[0].i), float(w.c[1].r), float(w.c[1].i)};
-    ksp[(b + 1) * S + off] = float4{float(w.c[2].r), float(w.c[2].i), float(w.c[3].r), float(w.c[3].i)};
+    const int b = (2 * j + (lam > 0 ? 1 : 0)) * 2 * NV;
+    T x[8];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) { x[2 * c] = w.c[c].r; x[2 * c + 1] = w.c[c].i; }
+#pragma unroll
+    for (int h = 0; h < 2 * NV; ++h) ksp[(b + h) * S + off] = pack(x + h * (4 / NV));
   }
 };
 
@@ -186,43 +207,56 @@ __global__ __launch_bounds__(256) void me_kernel_kc(const double* __restrict__ m
   if (out) store_me(prm, out, e, acc * (P::coupling_factor(prm) / (P::CDEN * P::IDEN)));
 }
 
-// Mixed form with the vector-ALU colour sum and the full kinematic cache
-// (propagator factors, polarisation bases, momentum sums and both helicity
-// states of the external spinors, in FP32): a block of W waves evaluates 64
-// events, wave w the helicities w, w + W, ... of each, so one per-event cache,
-// formed by wave 0 before the helicity loop, serves W lanes.  The helicity
-// program reads no momenta, so none stay in registers across the loop.  Each
-// wave's helicity partial sums meet in LDS and wave 0 adds them in wave
-// order.  Lanes past the end of the batch evaluate the last event again
-// (every wave reaches both barriers) and store nothing.
-template <class P, int W>
+// Vector-ALU colour sum with the full kinematic cache (propagator factors,
+// polarisation bases, momentum sums and both helicity states of the
+// external spinors): a block of W waves evaluates 64 events, wave w the
+// helicities w, w + W, ... of each, so one per-event cache, formed by wave 0
+// before the helicity loop, serves W lanes.  The helicity program reads no
+// momenta, so none stay in registers across the loop.  Each wave's helicity
+// partial sums meet in LDS and wave 0 adds them in wave order.  Lanes past
+// the end of the batch evaluate the last event again (every wave reaches
+// both barriers) and store nothing.  T = float: mixed form (out_hel unused);
+// T = double: FP64 form (out_hel as in me_kernel).
+template <class P, class T, int W>
 __global__ __launch_bounds__(64 * W) void me_kernel_kcw(const double* __restrict__ mom, int64_t nevt,
-                                                         double* __restrict__ out, const MeParams prm) {
-  constexpr int KR = P::KC_RE_F32, KC = P::KC_CX_F32, KE = P::KC_EPS_F32;
-  constexpr int KM = P::KC_MOM_F32, KS = P::KC_SP_F32;
-  __shared__ float kre[(KR > 0 ? KR : 1) * 64];
-  __shared__ cx<float> kcx[(KC > 0 ? KC : 1) * 64];
-  __shared__ float keps[5 * (KE > 0 ? KE : 1) * 64];
-  __shared__ float4 kmo[(KM > 0 ? KM : 1) * 64];
-  __shared__ float4 ksp[4 * (KS > 0 ? KS : 1) * 64];
+                                                         double* __restrict__ out, double* __restrict__ out_hel,
+                                                         const MeParams prm) {
+  constexpr bool F64 = sizeof(T) == 8;
+  constexpr int KR = F64 ? P::KC_RE_F64 : P::KC_RE_F32, KC = F64 ? P::KC_CX_F64 : P::KC_CX_F32;
+  constexpr int KE = F64 ? P::KC_EPS_F64 : P::KC_EPS_F32;
+  constexpr int KM = F64 ? P::KC_MOM_F64 : P::KC_MOM_F32, KS = F64 ? P::KC_SP_F64 : P::KC_SP_F32;
+  using DC = LdsKinCache<T, 64, true>;
+  constexpr int NV = DC::NV;
+  __shared__ T kre[(KR > 0 ? KR : 1) * 64];
+  __shared__ cx<T> kcx[(KC > 0 ? KC : 1) * 64];
+  __shared__ T keps[5 * (KE > 0 ? KE : 1) * 64];
+  __shared__ typename DC::V kmo[NV * (KM > 0 ? KM : 1) * 64];
+  __shared__ typename DC::V ksp[4 * NV * (KS > 0 ? KS : 1) * 64];
   __shared__ double part[W * 64];
   const int lane = threadIdx.x % 64;
   const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / 64);
   const int64_t e = int64_t(blockIdx.x) * 64 + lane;
   const bool live = e < nevt;
   const int64_t ec = live ? e : nevt - 1;
-  LdsKinCache<float, 64, true> dc{kre, kcx, keps, lane, kmo, ksp};
+  DC dc{kre, kcx, keps, lane, kmo, ksp};
   double p[P::NPAR][4];
   load_on_shell<P::MASSIVE>(mom + ec * (4 * P::NPAR), p, prm.mt);
-  if (wave == 0) P::template den_fill_f32<float>(p, prm, dc);
+  if (wave == 0) {
+    if constexpr (F64) P::template den_fill_f64<T>(p, prm, dc);
+    else P::template den_fill_f32<T>(p, prm, dc);
+  }
   __syncthreads();
   double acc = 0.0;
   for (int ih = wave; ih < prm.nhel; ih += W) {
     asm volatile("" : "+v"(dc.off));
     const unsigned hel = prm.hel[ih];
-    cx<float> jamp[P::NCOLOR];
-    P::template amplitudes<float>(p, hel, prm, jamp, dc);
-    acc += double(P::template colour_sum<float>(jamp));
+    cx<T> jamp[P::NCOLOR];
+    P::template amplitudes<T>(p, hel, prm, jamp, dc);
+    const double q = double(P::template colour_sum<T>(jamp));
+    if constexpr (F64) {
+      if (out_hel && live) out_hel[e * P::NHEL + hel] = q * (P::coupling_factor(prm) / P::CDEN);
+    }
+    acc += q;
   }
   part[wave * 64 + lane] = acc;
   __syncthreads();
@@ -519,6 +553,12 @@ int launch(int mode, const double* mom, int64_t nevt, double* out, double* out_h
       const int64_t nb = (nevt + 127) / 128;
       hipLaunchKernelGGL((me_kernel_ldsjamp<P, double>), dim3(unsigned(nb)), dim3(128), 0, stream, mom, nevt,
                          out, out_hel, prm);
+    } else if constexpr (P::KC_MOM_F64 + P::KC_SP_F64 > 0) {
+      const int64_t nb = (nevt + 63) / 64;
+      if (nb > 0x7fffffffLL) return -1;
+      constexpr int W = P::F64_KCW_WAVES;
+      hipLaunchKernelGGL((me_kernel_kcw<P, double, W>), dim3(unsigned(nb)), dim3(64 * W), 0, stream, mom, nevt,
+                         out, out_hel, prm);
     } else if constexpr (P::KC_RE_F64 + P::KC_CX_F64 + P::KC_EPS_F64 > 0) {
       hipLaunchKernelGGL((me_kernel_kc<P, double>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
                          out_hel, prm);
@@ -553,7 +593,8 @@ int launch(int mode, const double* mom, int64_t nevt, double* out, double* out_h
       const int64_t nb = (nevt + 63) / 64;
       if (nb > 0x7fffffffLL) return -1;
       constexpr int W = P::F32_KC_WAVES;
-      hipLaunchKernelGGL((me_kernel_kcw<P, W>), dim3(unsigned(nb)), dim3(64 * W), 0, stream, mom, nevt, out, prm);
+      hipLaunchKernelGGL((me_kernel_kcw<P, float, W>), dim3(unsigned(nb)), dim3(64 * W), 0, stream, mom, nevt,
+                         out, nullptr, prm);
     } else if constexpr (P::KC_RE_F32 + P::KC_CX_F32 + P::KC_EPS_F32 > 0) {
       hipLaunchKernelGGL((me_kernel_kc<P, float>), dim3(unsigned(nblk)), dim3(block), 0, stream, mom, nevt, out,
                          nullptr, prm);

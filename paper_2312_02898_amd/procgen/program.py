@@ -865,6 +865,8 @@ def all_programs(budget=None):
         p.fp64_kc_waves = FP64_KC_WAVES.get(p.name, 1)
         p.mom_cache_f32 = p.name in MOM_CACHE_F32 and p.den_cache_f32
         p.f32_kc_waves = F32_KC_WAVES if p.mom_cache_f32 else 1
+        p.mom_cache_f64 = p.name in MOM_CACHE_F64 and p.den_cache_f64 and not p.fp64_lds_jamps
+        p.f64_kcw_waves = F64_KCW_WAVES if p.mom_cache_f64 else 1
         b64, i64 = DEFAULT_SCHEDULE_F64.get(p.name, (256, 4))
         b32, i32 = DEFAULT_SCHEDULE_F32.get(p.name, (512, 4))
         schedule(p, budget if budget is not None else b32, i32)
@@ -904,6 +906,10 @@ DEN_CACHE_F64 = {"ggttgg", "eemumu", "ggtt", "ggttg", "uutt", "uxutt", "uuttg", 
 # the q g > t t~ q g channels and g g > t t~ u u~, where it made no gain
 MOM_CACHE_F32 = DEN_CACHE_F32 - {"ugttug", "guttug", "uxgttuxg", "guxttuxg", "ggttuux"}
 F32_KC_WAVES = 2
+# the same for the FP64 forms whose jamps stay in registers (FP64 entries
+# take twice the LDS: F64_KCW_WAVES waves share one cache)
+MOM_CACHE_F64 = DEN_CACHE_F64 - {"ggttgg"}
+F64_KCW_WAVES = 4
 # processes whose default mixed form (ME_MIXED) sums colours on FP16 hi+lo
 # MFMA; the others use the vector ALU (chosen by measurement on 2^20 events
 # of each process's configuration)

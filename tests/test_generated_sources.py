@@ -44,3 +44,4 @@ def test_shipped_schedule_parameters():
     assert "ggttgg" in program.DEN_CACHE_F64
     assert program.MOM_CACHE_F32 == program.DEN_CACHE_F32 - {"ugttug", "guttug", "uxgttuxg", "guxttuxg", "ggttuux"}
     assert program.F32_KC_WAVES == 2
+    assert program.MOM_CACHE_F64 == program.DEN_CACHE_F64 - {"ggttgg"} and program.F64_KCW_WAVES == 4
