@@ -36,10 +36,10 @@ FP64_VECTOR_PEAK = 78.6e12    # MI355X fp64 vector FLOP/s
 # otherwise.
 PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 MEASURED_TRAFFIC = {
-    "valu": {"digest": "0ef09884c3e4225b", "fetch_kib": 99030, "write_kib": 8192},
-    "mfma_f16_hilo": {"digest": "7475b8ae07de03f0", "fetch_kib": 99044, "write_kib": 8192},
-    "mfma_bf16_hilo": {"digest": "55199d4cbc46879d", "fetch_kib": 99044, "write_kib": 8192},
-    "fp64": {"digest": "271db46bab37b7a9", "fetch_kib": 99690, "write_kib": 8192},
+    "valu": {"digest": "6937676ab1a6ff54", "fetch_kib": 98950, "write_kib": 8192},
+    "mfma_f16_hilo": {"digest": "f869b6f510a2b15f", "fetch_kib": 98972, "write_kib": 8192},
+    "mfma_bf16_hilo": {"digest": "4f49e968d10c435a", "fetch_kib": 98964, "write_kib": 8192},
+    "fp64": {"digest": "fc91d28f865b6ea9", "fetch_kib": 99546, "write_kib": 8192},
 }
 
 
@@ -71,7 +71,7 @@ def kernel_digest(variant):
         kh = fh.read()
     names = {"valu": ("void me_kernel_kcw(",), "mfma_f16_hilo": ("void me_mfma_body_w(", "void me_kernel_mfma("),
              "mfma_bf16_hilo": ("void me_mfma_body_w(", "void me_kernel_mfma_bf16("),
-             "fp64": ("void me_kernel_ldsjamp_kc(",)}[variant]
+             "fp64": ("void me_kernel_kcw(",)}[variant]
     for name in names:
         a = kh.rindex("template", 0, kh.index(name))
         h.update(kh[a:kh.index("\n}\n", a)].encode())
@@ -197,7 +197,7 @@ def main():
     r64 = out64.cpu().numpy()
     forms = {"mfma_f16_hilo": (me_mfma, "me_kernel_mfma<Proc_ggttgg, false>"),
              "mfma_bf16_hilo": (me_bf16, "me_kernel_mfma_bf16<Proc_ggttgg>"),
-             "valu": (me_valu, "me_kernel_kcw<Proc_ggttgg, 2>")}
+             "valu": (me_valu, "me_kernel_kcw<Proc_ggttgg, float, 2>")}
     variants, timed = {}, {}
     for form, (mef, kname) in forms.items():
         o = torch.empty(args.nevt, dtype=torch.float64, device=dev)
@@ -257,7 +257,7 @@ def main():
         "roofline_fp64": {"bound": "alu", "achieved": ach64 / 1e12, "peak": FP64_VECTOR_PEAK / 1e12,
                           "unit": "TFLOP/s", "frac": ach64 / FP64_VECTOR_PEAK, "traffic": measured_traffic("fp64"),
                           "algorithmic_bytes": n * info["bytes_per_event"],
-                          "kernel": "me_kernel_ldsjamp_kc<Proc_ggttgg, 2>", "kernel_ms": t_launch64 * 1e3},
+                          "kernel": "me_kernel_kcw<Proc_ggttgg, double, 4>", "kernel_ms": t_launch64 * 1e3},
     }
 
     # gg -> t tbar ggg (1240 diagrams, 120 colour flows), split form: part

@@ -879,12 +879,13 @@ def all_programs(budget=None):
 # (budget in FP64 dwords, greedy passes) per process and arithmetic type,
 # and whether amplitudes share half contractions; chosen by measurement on
 # gfx950 (2^20 gg -> t tbar gg events)
-DEFAULT_SCHEDULE_F64 = {"eemumu": (256, 4), "ggtt": (256, 4), "ggttg": (256, 4), "ggttgg": (240, 4)}
+DEFAULT_SCHEDULE_F64 = {"eemumu": (256, 4), "ggtt": (256, 4), "ggttg": (256, 4), "ggttgg": (232, 4)}
 DEFAULT_SCHEDULE_F32 = {"eemumu": (256, 4), "ggtt": (256, 4), "ggttg": (384, 1), "ggttgg": (448, 2)}
 SHARE_HALF = {"ggttg": False, "ggttgg": False, "ggttggg": True}
 # FP64 forms that keep their jamps in LDS (frees 4 registers per colour flow
-# for the wavefunction schedule; gg -> t tbar gg FP64 91 -> 79 ms per 2^20)
-FP64_LDS_JAMPS = {"ggttgg"}
+# for the wavefunction schedule; none since the momentum sums and spinors
+# left the registers for the per-event cache)
+FP64_LDS_JAMPS = set()
 # the same for the mixed form's vector-ALU kernel
 F32_LDS_JAMPS = set()
 # waves per block that share one event's kinematic cache in the FP64 form
@@ -907,8 +908,9 @@ DEN_CACHE_F64 = {"ggttgg", "eemumu", "ggtt", "ggttg", "uutt", "uxutt", "uuttg", 
 MOM_CACHE_F32 = DEN_CACHE_F32 - {"ugttug", "guttug", "uxgttuxg", "guxttuxg", "ggttuux"}
 F32_KC_WAVES = 2
 # the same for the FP64 forms whose jamps stay in registers (FP64 entries
-# take twice the LDS: F64_KCW_WAVES waves share one cache)
-MOM_CACHE_F64 = DEN_CACHE_F64 - {"ggttgg"}
+# take twice the LDS: F64_KCW_WAVES waves share one cache; gg -> t tbar gg
+# FP64 54.2 -> 41.3 ms per 2^20 events against jamps in LDS)
+MOM_CACHE_F64 = set(DEN_CACHE_F64)
 F64_KCW_WAVES = 4
 # processes whose default mixed form (ME_MIXED) sums colours on FP16 hi+lo
 # MFMA; the others use the vector ALU (chosen by measurement on 2^20 events
