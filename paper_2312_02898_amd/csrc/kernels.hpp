@@ -333,59 +333,6 @@ __global__ __launch_bounds__(128) void me_kernel_ldsjamp(const double* __restric
   if (out) store_me(prm, out, e, acc * (P::coupling_factor(prm) / (P::CDEN * P::IDEN)));
 }
 
-// FP64 form with the jamps in LDS and the kinematic cache, for processes
-// whose jamps and cache do not both fit beside one event per lane: a block of
-// W waves evaluates 64 events, wave w the helicities w, w + W, w + 2W, ... of
-// each, so the per-event cache (propagator factors and polarisation bases,
-// formed by wave 0 before the helicity loop) serves W lanes and its LDS per
-// lane shrinks W-fold.  Each wave's helicity partial sums meet in LDS and
-// wave 0 adds them in wave order (a fixed order: the result does not depend
-// on timing).  Lanes past the end of the batch evaluate the last event again
-// (every wave reaches both barriers) and store nothing.
-template <class P, int W>
-__global__ __launch_bounds__(64 * W) void me_kernel_ldsjamp_kc(const double* __restrict__ mom, int64_t nevt,
-                                                                double* __restrict__ out,
-                                                                double* __restrict__ out_hel, const MeParams prm) {
-  constexpr int KR = P::KC_RE_F64, KC = P::KC_CX_F64, KE = P::KC_EPS_F64;
-  __shared__ double kre[(KR > 0 ? KR : 1) * 64];
-  __shared__ cx<double> kcx[(KC > 0 ? KC : 1) * 64];
-  __shared__ double keps[5 * (KE > 0 ? KE : 1) * 64];
-  __shared__ cx<double> lds[W * P::NCOLOR * 64];
-  __shared__ double part[W * 64];
-  const int lane = threadIdx.x % 64;
-  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / 64);
-  const int64_t e = int64_t(blockIdx.x) * 64 + lane;
-  const bool live = e < nevt;
-  const int64_t ec = live ? e : nevt - 1;
-  LdsJamps<double> jamp{lds + wave * P::NCOLOR * 64 + lane};
-  double p[P::NPAR][4];
-  load_on_shell<P::MASSIVE>(mom + ec * (4 * P::NPAR), p, prm.mt);
-  LdsKinCache<double, 64> dc{kre, kcx, keps, lane};
-  if (wave == 0) P::template den_fill_f64<double>(p, prm, dc);
-  __syncthreads();
-  double acc = 0.0;
-  for (int ih = wave; ih < prm.nhel; ih += W) {
-#pragma unroll
-    for (int i = 0; i < P::NPAR; ++i)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) asm volatile("" : "+v"(p[i][c]));
-    asm volatile("" : "+v"(dc.off));
-    const unsigned hel = prm.hel[ih];
-    P::template amplitudes<double>(p, hel, prm, jamp, dc);
-    const double q = P::template colour_sum<double>(jamp);
-    if (out_hel && live) out_hel[e * P::NHEL + hel] = q * (P::coupling_factor(prm) / P::CDEN);
-    acc += q;
-  }
-  part[wave * 64 + lane] = acc;
-  __syncthreads();
-  if (wave == 0 && live && out) {
-    double s = 0.0;
-#pragma unroll
-    for (int w = 0; w < W; ++w) s += part[w * 64 + lane];
-    store_me(prm, out, e, s * (P::coupling_factor(prm) / (P::CDEN * P::IDEN)));
-  }
-}
-
 // Mixed form with the colour sum on MFMA.  Every lane of a wave stays active
 // through the helicity loop (the MFMA needs the whole wave); lanes past the
 // end of the batch evaluate the last event again and do not store.  The
@@ -543,13 +490,7 @@ int launch(int mode, const double* mom, int64_t nevt, double* out, double* out_h
   if (nblk > 0x7fffffffLL) return -1;
   if (mode == ME_MODE_FP64) {
     // one FP64 kernel per process, chosen when the process is generated
-    if constexpr (P::FP64_LDS_JAMPS && P::KC_RE_F64 + P::KC_CX_F64 + P::KC_EPS_F64 > 0) {
-      const int64_t nb = (nevt + 63) / 64;
-      if (nb > 0x7fffffffLL) return -1;
-      constexpr int W = P::FP64_KC_WAVES;
-      hipLaunchKernelGGL((me_kernel_ldsjamp_kc<P, W>), dim3(unsigned(nb)), dim3(64 * W), 0, stream, mom, nevt,
-                         out, out_hel, prm);
-    } else if constexpr (P::FP64_LDS_JAMPS) {
+    if constexpr (P::FP64_LDS_JAMPS) {
       const int64_t nb = (nevt + 127) / 128;
       hipLaunchKernelGGL((me_kernel_ldsjamp<P, double>), dim3(unsigned(nb)), dim3(128), 0, stream, mom, nevt,
                          out, out_hel, prm);

@@ -861,8 +861,7 @@ def all_programs(budget=None):
         p.f32_lds_jamps = p.name in F32_LDS_JAMPS
         p.mixed_mfma = p.name in MIXED_MFMA
         p.den_cache_f32 = p.name in DEN_CACHE_F32
-        p.den_cache_f64 = p.name in DEN_CACHE_F64
-        p.fp64_kc_waves = FP64_KC_WAVES.get(p.name, 1)
+        p.den_cache_f64 = p.name in DEN_CACHE_F64 and not p.fp64_lds_jamps
         p.mom_cache_f32 = p.name in MOM_CACHE_F32 and p.den_cache_f32
         p.f32_kc_waves = F32_KC_WAVES if p.mom_cache_f32 else 1
         p.mom_cache_f64 = p.name in MOM_CACHE_F64 and p.den_cache_f64 and not p.fp64_lds_jamps
@@ -888,16 +887,12 @@ SHARE_HALF = {"ggttg": False, "ggttgg": False, "ggttggg": True}
 FP64_LDS_JAMPS = set()
 # the same for the mixed form's vector-ALU kernel
 F32_LDS_JAMPS = set()
-# waves per block that share one event's kinematic cache in the FP64 form
-# with jamps in LDS
-FP64_KC_WAVES = {"ggttgg": 2}
 # mixed forms whose vector-ALU kernel forms the propagator factors once per
 # event into LDS instead of once per helicity
 DEN_CACHE_F32 = {"eemumu", "ggtt", "ggttg", "ggttgg", "uutt", "uxutt", "uuttg", "uxuttg", "ugttu", "guttu",
                  "uxgttux", "guxttux", "uuttgg", "uxuttgg", "ugttug", "guttug", "uxgttuxg", "guxttuxg", "ggttuux",
                  "uuttuux", "uuttddx", "uuttuu", "udttud", "uxuxttuxux"}
-# the same for the FP64 forms (with jamps in LDS: the helicities of an event
-# are spread over FP64_KC_WAVES waves that share one cache)
+# the same for the FP64 forms whose jamps stay in registers
 DEN_CACHE_F64 = {"ggttgg", "eemumu", "ggtt", "ggttg", "uutt", "uxutt", "uuttg", "uxuttg", "ugttu", "guttu", "uxgttux",
                  "guxttux", "uuttgg", "uxuttgg", "ugttug", "guttug", "uxgttuxg", "guxttuxg", "ggttuux",
                  "uuttuux", "uuttddx", "uuttuu", "udttud", "uxuxttuxux"}
