@@ -18,9 +18,14 @@
  *     "u u~ > t t~"  "u~ u > t t~"                      (p p > t t~, quark channels)
  *     "u u~ > t t~ g"  "u~ u > t t~ g"  "u g > t t~ u"  "g u > t t~ u"
  *     "u~ g > t t~ u~"  "g u~ > t t~ u~"               (p p > t t~ + 1 jet)
+ *     "u u~ > t t~ g g"  "u~ u > t t~ g g"  "u g > t t~ u g"  "g u > t t~ u g"
+ *     "u~ g > t t~ u~ g"  "g u~ > t t~ u~ g"  "g g > t t~ u u~"
+ *     "u u~ > t t~ u u~"  "u u~ > t t~ d d~"  "u u > t t~ u u"
+ *     "u d > t t~ u d"  "u~ u~ > t t~ u~ u~"          (p p > t t~ + 2 jets)
  * The short names "eemumu", "ggtt", "ggttg", "ggttgg", "ggttggg", "uutt",
- * "uxutt", "uuttg", "uxuttg", "ugttu", "guttu", "uxgttux", "guxttux" are
- * accepted too.  "g g > t t~ g g g" runs in a split form whose jamp
+ * "uxutt", "uuttg", "uxuttg", "ugttu", "guttu", "uxgttux", "guxttux",
+ * "uuttgg", "uxuttgg", "ugttug", "guttug", "uxgttuxg", "guxttuxg", "ggttuux",
+ * "uuttuux", "uuttddx", "uuttuu", "udttud", "uxuxttuxux" are accepted too.  "g g > t t~ g g g" runs in a split form whose jamp
  * workspace (me_workspace_bytes) comes from the stream-ordered allocator.
  *
  * Conventions
