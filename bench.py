@@ -36,9 +36,9 @@ FP64_VECTOR_PEAK = 78.6e12    # MI355X fp64 vector FLOP/s
 # otherwise.
 PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 MEASURED_TRAFFIC = {
-    "valu": {"digest": "6937676ab1a6ff54", "fetch_kib": 98950, "write_kib": 8192},
-    "mfma_f16_hilo": {"digest": "f869b6f510a2b15f", "fetch_kib": 98972, "write_kib": 8192},
-    "mfma_bf16_hilo": {"digest": "4f49e968d10c435a", "fetch_kib": 98964, "write_kib": 8192},
+    "valu": {"digest": "621b3095d35e88ea", "fetch_kib": 98944, "write_kib": 8192},
+    "mfma_f16_hilo": {"digest": "b1c3e8102cfe8aa2", "fetch_kib": 98964, "write_kib": 8192},
+    "mfma_bf16_hilo": {"digest": "5a9ad9d38557ea06", "fetch_kib": 98956, "write_kib": 8192},
     "fp64": {"digest": "fc91d28f865b6ea9", "fetch_kib": 99546, "write_kib": 8192},
 }
 

@@ -866,8 +866,8 @@ def all_programs(budget=None):
         p.f32_kc_waves = F32_KC_WAVES if p.mom_cache_f32 else 1
         p.mom_cache_f64 = p.name in MOM_CACHE_F64 and p.den_cache_f64 and not p.fp64_lds_jamps
         p.f64_kcw_waves = F64_KCW_WAVES if p.mom_cache_f64 else 1
-        b64, i64 = DEFAULT_SCHEDULE_F64.get(p.name, (256, 4))
-        b32, i32 = DEFAULT_SCHEDULE_F32.get(p.name, (512, 4))
+        b64, i64 = DEFAULT_SCHEDULE_F64.get(p.name, SCHEDULE_F64_OTHERS)
+        b32, i32 = DEFAULT_SCHEDULE_F32.get(p.name, SCHEDULE_F32_OTHERS)
         schedule(p, budget if budget is not None else b32, i32)
         p.ops_f32 = p.ops
         schedule(p, budget if budget is not None else b64, i64)
@@ -878,8 +878,15 @@ def all_programs(budget=None):
 # (budget in FP64 dwords, greedy passes) per process and arithmetic type,
 # and whether amplitudes share half contractions; chosen by measurement on
 # gfx950 (2^20 gg -> t tbar gg events)
-DEFAULT_SCHEDULE_F64 = {"eemumu": (256, 4), "ggtt": (256, 4), "ggttg": (256, 4), "ggttgg": (232, 4)}
-DEFAULT_SCHEDULE_F32 = {"eemumu": (256, 4), "ggtt": (256, 4), "ggttg": (384, 1), "ggttgg": (448, 2)}
+# (with the momentum sums and spinors in the per-event cache, registers that
+# the schedule can use grew: budgets of 1024 (no eviction) for the FP32 forms
+# and 512 for the FP64 ones measured fastest, except where noted)
+DEFAULT_SCHEDULE_F64 = {"eemumu": (512, 4), "ggtt": (512, 4), "ggttg": (512, 4), "ggttgg": (232, 4)}
+DEFAULT_SCHEDULE_F32 = {"eemumu": (1024, 4), "ggtt": (1024, 4), "ggttg": (1024, 1), "ggttgg": (1024, 2),
+                        # the q g > t t~ q g channels ran 40 % slower at 1024
+                        "ugttug": (512, 4), "guttug": (512, 4), "uxgttuxg": (512, 4), "guxttuxg": (512, 4)}
+SCHEDULE_F64_OTHERS = (512, 4)
+SCHEDULE_F32_OTHERS = (1024, 4)
 SHARE_HALF = {"ggttg": False, "ggttgg": False, "ggttggg": True}
 # FP64 forms that keep their jamps in LDS (frees 4 registers per colour flow
 # for the wavefunction schedule; none since the momentum sums and spinors
