@@ -36,10 +36,10 @@ FP64_VECTOR_PEAK = 78.6e12    # MI355X fp64 vector FLOP/s
 # otherwise.
 PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 MEASURED_TRAFFIC = {
-    "valu": {"digest": "621b3095d35e88ea", "fetch_kib": 98944, "write_kib": 8192},
-    "mfma_f16_hilo": {"digest": "b1c3e8102cfe8aa2", "fetch_kib": 98964, "write_kib": 8192},
-    "mfma_bf16_hilo": {"digest": "5a9ad9d38557ea06", "fetch_kib": 98956, "write_kib": 8192},
-    "fp64": {"digest": "fc91d28f865b6ea9", "fetch_kib": 99546, "write_kib": 8192},
+    "valu": {"digest": "be242927370cdee1", "fetch_kib": 98908, "write_kib": 8192},
+    "mfma_f16_hilo": {"digest": "59e82bada25ee17a", "fetch_kib": 98932, "write_kib": 9984},
+    "mfma_bf16_hilo": {"digest": "6106ce334bf67df4", "fetch_kib": 98925, "write_kib": 9984},
+    "fp64": {"digest": "30bfd2fa76e4cbeb", "fetch_kib": 99398, "write_kib": 8192},
 }
 
 
