@@ -881,7 +881,7 @@ def all_programs(budget=None):
 # (with the momentum sums and spinors in the per-event cache, registers that
 # the schedule can use grew: budgets of 1024 (no eviction) for the FP32 forms
 # and 512 for the FP64 ones measured fastest, except where noted)
-DEFAULT_SCHEDULE_F64 = {"eemumu": (512, 4), "ggtt": (512, 4), "ggttg": (512, 4), "ggttgg": (248, 4)}
+DEFAULT_SCHEDULE_F64 = {"eemumu": (512, 4), "ggtt": (512, 4), "ggttg": (512, 4), "ggttgg": (250, 4)}
 DEFAULT_SCHEDULE_F32 = {"eemumu": (1024, 4), "ggtt": (1024, 4), "ggttg": (1024, 1), "ggttgg": (1024, 2),
                         # the q g > t t~ q g channels ran 40 % slower at 1024
                         "ugttug": (512, 4), "guttug": (512, 4), "uxgttuxg": (512, 4), "guxttuxg": (512, 4)}
